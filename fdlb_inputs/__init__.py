@@ -1,0 +1,229 @@
+"""Seeded synthetic inputs for the FDLB hot path: workload parameters and initial fields.
+
+This module is shared by the CPU oracle's tests and by the GPU path's tests and benchmark.
+It holds none of the lattice Boltzmann arithmetic: it only builds parameter sets and the
+macroscopic initial fields (rho, u_x, u_y, T) on the grid, plus the gas-dynamics jump
+conditions that fix the post-shock states of the reflection problems.
+
+Conventions
+-----------
+* A problem is a plain dict: ``nx, ny, dx, dy, dt, tau, lam, v, bc, bc_state`` where ``bc``
+  lists the kinds of the sides (x-, x+, y-, y+) and ``bc_state`` the (rho, ux, uy, T) each
+  Dirichlet side imposes.
+* Fields are float64 arrays of shape (ny, nx), row-major (x fastest).
+* Cell centres sit at ((i + 1/2) dx, (j + 1/2) dy).
+* Density is the particle number density n (particle mass m = 1, Sec. 2 of the paper) and
+  T is theta = T/m.
+* The gas of the Watari-Tsutahara model has internal energy n T in two dimensions, so the
+  ratio of specific heats is gamma = 2; the post-shock states printed in Sec. 5.2 of the
+  paper are reproduced by the jump conditions below with that gamma.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Boundary kinds; the integer codes are the ones the C interfaces take.
+PERIODIC, OUTFLOW, DIRICHLET, WALL = 0, 1, 2, 3
+BC_NAMES = {"periodic": PERIODIC, "outflow": OUTFLOW, "dirichlet": DIRICHLET, "wall": WALL}
+
+# Particle speeds v1..v4 of the discrete-velocity model used throughout the paper
+# (Sec. 4, parameters of Fig. 2).
+V_WT = (1.0, 1.92, 2.99, 4.49)
+
+GAMMA_WT = 2.0
+
+
+def problem(nx, ny, dx, dt, tau, lam, bc, bc_state=None, dy=None, v=V_WT, name=""):
+    """Parameter dict of one problem.  ``bc`` is four kinds (names or codes)."""
+    kinds = tuple(BC_NAMES[b] if isinstance(b, str) else int(b) for b in bc)
+    states = [(1.0, 0.0, 0.0, 1.0)] * 4 if bc_state is None else [tuple(map(float, s)) for s in bc_state]
+    return dict(name=name, nx=int(nx), ny=int(ny), dx=float(dx), dy=float(dx if dy is None else dy),
+                dt=float(dt), tau=float(tau), lam=float(lam), v=tuple(map(float, v)),
+                bc=kinds, bc_state=tuple(states))
+
+
+def uniform_fields(nx, ny, state):
+    rho, ux, uy, T = map(float, state)
+    shape = (ny, nx)
+    return (np.full(shape, rho), np.full(shape, ux), np.full(shape, uy), np.full(shape, T))
+
+
+def riemann_fields(nx, ny, left, right, split=None):
+    """Piecewise-constant Riemann data: cells i < split get ``left``, the others ``right``.
+
+    The default split is nx // 2, i.e. the discontinuity sits at the middle of the tube
+    between cells nx/2 - 1 and nx/2."""
+    split = nx // 2 if split is None else split
+    out = []
+    for a, b in zip(left, right):
+        row = np.where(np.arange(nx) < split, float(a), float(b))
+        out.append(np.ascontiguousarray(np.broadcast_to(row, (ny, nx))).astype(np.float64))
+    return tuple(out)
+
+
+def smooth_random_fields(nx, ny, seed, base=(1.0, 0.3, -0.2, 1.0), amp=(0.1, 0.1, 0.1, 0.1),
+                         modes=3):
+    """Seeded smooth periodic perturbation of a base state (sum of a few Fourier modes)."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    out = []
+    for b, a in zip(base, amp):
+        fld = np.full((ny, nx), float(b))
+        for _ in range(modes):
+            kx, ky = rng.integers(0, 3, size=2)
+            ph = rng.uniform(0, 2 * np.pi)
+            fld += a / modes * rng.uniform(-1, 1) * np.cos(2 * np.pi * (kx * X + ky * Y) + ph)
+        out.append(np.ascontiguousarray(fld))
+    return tuple(out)
+
+
+def random_fields(nx, ny, seed, base=(1.0, 0.3, -0.2, 1.0), amp=(0.05, 0.05, 0.05, 0.05)):
+    """Seeded cell-by-cell noise around a base state (exercises every stencil weight)."""
+    rng = np.random.default_rng(seed)
+    return tuple(np.ascontiguousarray(float(b) + float(a) * rng.uniform(-1, 1, size=(ny, nx)))
+                 for b, a in zip(base, amp))
+
+
+# --------------------------------------------------------------------------------------
+# Jump conditions (gamma = 2) for the reflection problems of Sec. 5.2
+# --------------------------------------------------------------------------------------
+
+def oblique_shock_state(pre, mach_n=None, beta_deg=30.0, gamma=GAMMA_WT):
+    """Post-shock state behind a steady oblique shock.
+
+    ``pre`` = (rho, u, 0, T) flows along +x.  The shock line falls from the top-left corner
+    at angle beta to the x-axis; its unit normal towards the post-shock side is
+    (sin beta, cos beta).  If ``mach_n`` is given, ``u`` is replaced so that the upstream
+    normal Mach number equals it.  Returns (rho2, ux2, uy2, T2)."""
+    rho1, u1, v1, T1 = map(float, pre)
+    if v1 != 0.0:
+        raise ValueError("pre-shock flow must be along x")
+    beta = math.radians(beta_deg)
+    c1 = math.sqrt(gamma * T1)
+    if mach_n is not None:
+        u1 = mach_n * c1 / math.sin(beta)
+    wn1 = u1 * math.sin(beta)
+    m2 = (wn1 / c1) ** 2
+    r = (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p1 = rho1 * T1
+    p2 = p1 * (1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0))
+    rho2 = rho1 * r
+    wn2 = wn1 / r
+    wt = u1 * math.cos(beta)
+    ux2 = wt * math.cos(beta) + wn2 * math.sin(beta)
+    uy2 = -wt * math.sin(beta) + wn2 * math.cos(beta)
+    return (rho2, ux2, uy2, p2 / rho2), (rho1, u1, 0.0, T1)
+
+
+def moving_shock_state(pre_rho, pre_T, mach, direction_deg, gamma=GAMMA_WT):
+    """State behind a normal shock of Mach ``mach`` running into gas at rest; the gas
+    behind moves along ``direction_deg``.  Returns (rho2, ux2, uy2, T2)."""
+    c1 = math.sqrt(gamma * pre_T)
+    m2 = mach * mach
+    r = (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = pre_rho * pre_T * (1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0))
+    rho2 = pre_rho * r
+    speed = mach * c1 * (1.0 - 1.0 / r)
+    d = math.radians(direction_deg)
+    return (rho2, speed * math.cos(d), speed * math.sin(d), p2 / rho2)
+
+
+def reflection_fields(nx, ny, dx, pre, post, beta_deg, dy=None):
+    """Initial field of the steady regular reflection: post-shock above the incident shock
+    line y = Ly - x tan(beta) drawn from the top-left corner, pre-shock below."""
+    dy = dx if dy is None else dy
+    Ly = ny * dy
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    X, Y = np.meshgrid(x, y)
+    above = Y >= Ly - X * math.tan(math.radians(beta_deg))
+    return tuple(np.ascontiguousarray(np.where(above, float(b), float(a))) for a, b in zip(pre, post))
+
+
+# --------------------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------------------
+
+SOD_L, SOD_R = (1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.8)        # Sec. 5.1.1
+LAX_L, LAX_R = (0.445, 0.698, 0.0, 7.928), (0.5, 0.0, 0.0, 1.142)  # Sec. 5.1.2
+COL_L, COL_R = (1.0, 0.0, 0.0, 1000.0), (1.0, 0.0, 0.0, 0.01)      # Sec. 5.1.4
+TWO_L, TWO_R = (5.99924, 19.5975, 0.0, 76.8254), (5.99242, -6.19633, 0.0, 7.69222)  # Sec. 5.1.5
+REFL_PRE = (1.0, 20.0, 0.0, 0.5)                                   # Sec. 5.2.1 inflow
+REFL_POST_PRINTED = (50.0 / 17.0, 16.7, -5.71578, 22.61)           # Sec. 5.2.1 top state
+DMR_PRE = (2.0, 0.0, 0.0, 0.5)                                     # Sec. 5.2.2
+DMR_POST_PRINTED = (400.0 / 67.0, 13.3 * math.cos(math.radians(30.0)),
+                    -13.3 * math.sin(math.radians(30.0)), 89.2775)
+
+TUBE_BC = ("outflow", "outflow", "periodic", "periodic")
+
+
+def sod_tube(nx=400, ny=4, dx=2.5e-3, dt=1e-5, tau=2e-5, lam=2.0):
+    """Sod tube (Sec. 5.1.1 states) on the 400 x 4 grid, 1000 steps to t = 0.01."""
+    p = problem(nx, ny, dx, dt, tau, lam, TUBE_BC, name="sod_400x4")
+    return p, riemann_fields(nx, ny, SOD_L, SOD_R), 1000
+
+
+def colella_tube(nx=4000, ny=4, dx=2.5e-4, dt=1e-6, tau=2e-6, lam=20.0):
+    """Colella's explosion problem (Sec. 5.1.4 states, pressure ratio 1e5) on 4000 x 4,
+    20000 steps to t = 0.02."""
+    p = problem(nx, ny, dx, dt, tau, lam, TUBE_BC, name="colella_4000x4")
+    return p, riemann_fields(nx, ny, COL_L, COL_R), 20000
+
+
+def regular_reflection(nx, ny, dx, dt, tau, lam, pre, post, beta_deg, name):
+    """Steady regular reflection (Sec. 5.2.1): Dirichlet inflow on the left and post-shock
+    state on the top, reflecting wall at the bottom, outflow on the right."""
+    bc = ("dirichlet", "outflow", "wall", "dirichlet")
+    states = (pre, pre, pre, post)
+    p = problem(nx, ny, dx, dt, tau, lam, bc, states, name=name)
+    return p, reflection_fields(nx, ny, dx, pre, post, beta_deg)
+
+
+def reflection_1024x256(lam=2.0):
+    """Normal Mach 10 shock at 29 degrees to the wall, 1024 x 256, 40000 steps."""
+    post, pre = oblique_shock_state((1.0, 1.0, 0.0, 0.5), mach_n=10.0, beta_deg=29.0)
+    p, f = regular_reflection(1024, 256, 1e-3, 5e-6, 1e-5, lam, pre, post, 29.0,
+                              "reflection_mn10_29deg_1024x256")
+    return p, f, 40000
+
+
+def reflection_8192x2048(lam=2.0, nx=8192, ny=2048):
+    """Mach 20 inflow (1, 20, 0, 0.5) with the 30-degree incident shock of Sec. 5.2.1 on a
+    2.048 x 0.512 domain, 8192 x 2048 cells, 10000 steps."""
+    post, pre = oblique_shock_state(REFL_PRE, beta_deg=30.0)
+    p, f = regular_reflection(nx, ny, 2.5e-4, 1e-6, 2e-6, lam, pre, post, 30.0,
+                              f"reflection_m20_30deg_{nx}x{ny}")
+    return p, f, 10000
+
+
+def ensemble_draws(count=256, seed=0):
+    """Instance table of the batched tube ensemble: (nx, pressure ratio, density ratio)
+    drawn in this order per instance from ``numpy.random.default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        nx = int(rng.integers(256, 4097))
+        rp = float(10.0 ** rng.uniform(1.0, 5.0))
+        rr = float(rng.uniform(0.1, 10.0))
+        out.append((nx, rp, rr))
+    return out
+
+
+def ensemble_tubes(count=256, seed=0, ny=4):
+    """256 shock tubes on [0, 1] with left state (1, 0, 0, 1) and right density 1/r_rho,
+    pressure 1/r_p; dx = 1/nx, dt = 0.004 dx, tau = 2 dt; the artificial-viscosity
+    amplitude grows with log(r_p) from 2 (ratio 10, the Sod value) to 20 (ratio 1e5, the
+    Colella value).  5000 steps."""
+    probs = []
+    for i, (nx, rp, rr) in enumerate(ensemble_draws(count, seed)):
+        dx = 1.0 / nx
+        dt = 0.004 * dx
+        lam = 2.0 + 18.0 * math.log10(rp / 10.0) / 4.0
+        right = (1.0 / rr, 0.0, 0.0, rr / rp)
+        p = problem(nx, ny, dx, dt, 2.0 * dt, lam, TUBE_BC, name=f"tube{i}")
+        probs.append((p, riemann_fields(nx, ny, (1.0, 0.0, 0.0, 1.0), right)))
+    return probs, 5000
