@@ -1,0 +1,172 @@
+/*
+ * fdlb.h -- C interface of the MI355X finite-difference lattice Boltzmann (FDLB) solver for
+ * compressible flow at high Mach number: the model of Gan, Xu, Zhang, Yu and Li,
+ * "Two-dimensional lattice Boltzmann model for compressible flows with high Mach number"
+ * (arXiv:0801.4169).
+ *
+ * The problem statement follows the paper: a rectangular grid of nx x ny cells with spacing
+ * dx, dy (Sec. 5), the Watari-Tsutahara velocity set with speeds v1..v4 (Sec. 2,
+ * Eq. dvm_eq_1), the BGK relaxation time tau (Eq. bgk_eq), the time step dt and the
+ * artificial-viscosity amplitude lambda (Sec. 3, Eq. add4), an initial field of density,
+ * velocity and temperature, and a condition per side (Sec. 5.2: reflecting wall, outflow,
+ * Dirichlet; periodic for the one-dimensional tubes of Sec. 5.1).  One call to
+ * fdlb_step advances every distribution by Eq. (dis_eq1).
+ *
+ * Conventions
+ *  - Host fields (rho, ux, uy, T) are float64 arrays of ny rows of nx values (x fastest).
+ *  - Density is the particle number density n of Eq. (n_eq) (particle mass 1); T is
+ *    theta = T/m of Sec. 2; the pressure is P = n T (Eq. p_eq).
+ *  - Device memory is owned by the caller (for example a torch tensor) and borrowed for the
+ *    lifetime of a context.  The library allocates only small descriptor, tile-table and
+ *    reduction blocks of its own and frees them in fdlb_destroy.
+ *  - All work is enqueued on the HIP stream given at creation (NULL = the null stream).
+ *    Calls documented as "syncs" wait for that stream.
+ *  - Every call returns an fdlb_status; nothing throws across this interface.  A context
+ *    is not thread-safe; distinct contexts may be used from distinct threads.
+ *  - The device keeps a sticky non-physical flag (n <= 0, T <= 0, a non-finite moment, or
+ *    |u dt/dx| >= 1 in some cell after some step).  Calls that sync report it as
+ *    FDLB_ENONPHYS; the state is still readable.
+ */
+#ifndef FDLB_H
+#define FDLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdlb_ctx fdlb_ctx;
+
+typedef enum {
+    FDLB_OK = 0,
+    FDLB_EINVAL = 1,   /* bad argument: sizes, non-positive dx/dt/tau, Courant number >= 1,
+                          unpaired periodic sides, short buffer, wrong instance index */
+    FDLB_ENOMEM = 2,   /* the library's own small allocation failed */
+    FDLB_EDEVICE = 3,  /* a HIP call failed (the HIP error string is kept, fdlb_last_error) */
+    FDLB_ENONPHYS = 4, /* the non-physical flag is set (see above) */
+    FDLB_ESTATE = 5    /* call order: stepping or reading before a state was set */
+} fdlb_status;
+
+/* Storage and arithmetic of the distributions.
+ *   FDLB_F64: float64 storage and arithmetic.  The arithmetic follows one fixed evaluation
+ *             order without fused multiply-add, so it reproduces a plain float64
+ *             evaluation of the same formulas bit for bit.
+ *   FDLB_F32: float32 storage; equilibrium and stencil in float32; the moments
+ *             (density, velocity, temperature, pressure) are accumulated in float64. */
+typedef enum { FDLB_F64 = 0, FDLB_F32 = 1 } fdlb_precision;
+
+/* Side conditions (Sec. 5.2).  Sides are ordered x-, x+, y-, y+.
+ *   PERIODIC : wrap around; both sides of an axis must be periodic together.
+ *   OUTFLOW  : zero gradient, the ghost cells copy the edge cell ("supersonic outflow").
+ *   DIRICHLET: the ghost cells hold f^eq of the side's (rho, ux, uy, T).
+ *   WALL     : reflecting wall, the specular mirror of the cells inside about the cell
+ *              face (the velocity component normal to the wall reversed). */
+typedef enum {
+    FDLB_BC_PERIODIC = 0,
+    FDLB_BC_OUTFLOW = 1,
+    FDLB_BC_DIRICHLET = 2,
+    FDLB_BC_WALL = 3
+} fdlb_bc_kind;
+
+typedef struct {
+    int32_t kind;   /* fdlb_bc_kind */
+    int32_t pad_;
+    double rho, ux, uy, T; /* used by FDLB_BC_DIRICHLET only */
+} fdlb_bc;
+
+typedef struct {
+    int32_t nx, ny;      /* cells; nx, ny >= 2 (and >= 5 if the side is not periodic) */
+    double dx, dy;       /* cell sizes, > 0 */
+    double dt, tau;      /* time step and BGK relaxation time, > 0 (Eq. bgk_eq) */
+    double lambda;       /* artificial-viscosity amplitude, >= 0 (Eq. add4) */
+    double v[4];         /* speeds v1..v4 (Eq. dvm_eq_1); the paper uses 1, 1.92, 2.99, 4.49 */
+    fdlb_bc bc[4];       /* x-, x+, y-, y+ */
+    int32_t precision;   /* fdlb_precision */
+    int32_t tile;        /* tile shape id (fdlb_tile_shapes); 0 = library default */
+} fdlb_params;
+
+/* Bytes of device memory a context for these parameters borrows (both ping-pong halves:
+ * 33 distribution planes, the pressure plane and the wall-pressure rows).  0 if the
+ * parameters are invalid. */
+size_t fdlb_required_bytes(const fdlb_params *p);
+
+/* Creates a context.  `arena` is a device pointer to at least fdlb_required_bytes(p)
+ * bytes, 256-byte aligned, owned by the caller and kept alive until fdlb_destroy.
+ * `stream` is a hipStream_t (may be NULL).  The state is undefined until fdlb_set_state
+ * or fdlb_set_f.  Errors: FDLB_EINVAL (parameters, Courant number max|v| dt/dx >= 1,
+ * arena too small or misaligned), FDLB_ENOMEM, FDLB_EDEVICE. */
+fdlb_status fdlb_create(const fdlb_params *p, void *stream, void *arena, size_t arena_bytes,
+                        fdlb_ctx **out);
+
+/* Sets every f to the equilibrium of Eq. (feq_eq) for the given host fields (each nx*ny
+ * float64, row-major) and derives the pressure field.  Enqueued; the host arrays may be
+ * reused when the call returns (they are copied to device first and the call syncs on
+ * that copy).  Errors: FDLB_EINVAL (NULL field). */
+fdlb_status fdlb_set_state(fdlb_ctx *c, const double *rho, const double *ux, const double *uy,
+                           const double *T);
+
+/* As fdlb_set_state, but `fields` is a device pointer to 4 * nx * ny float64 values:
+ * rho, ux, uy, T planes, each row-major.  Asynchronous; the buffer must stay valid until
+ * the stream reaches this point. */
+fdlb_status fdlb_set_state_device(fdlb_ctx *c, const double *fields);
+
+/* Advances nsteps >= 0 time steps of Eq. (dis_eq1) (asynchronous).  Each step is one
+ * kernel launch over the grid; the launches are replayed from a captured HIP graph.
+ * Errors: FDLB_ESTATE (no state yet), FDLB_EINVAL (nsteps < 0), FDLB_EDEVICE. */
+fdlb_status fdlb_step(fdlb_ctx *c, int64_t nsteps);
+
+/* Density, velocity and temperature (Eqs. n_eq, nu_eq, p_eq) of the current state into
+ * host arrays of nx*ny float64 each.  Syncs.  Returns FDLB_ENONPHYS if the flag is set
+ * (the fields are still written). */
+fdlb_status fdlb_get_moments(fdlb_ctx *c, double *rho, double *ux, double *uy, double *T);
+
+/* As fdlb_get_moments into a device buffer of 4 * nx * ny float64 (rho, ux, uy, T
+ * planes).  Asynchronous; does not report the flag. */
+fdlb_status fdlb_get_moments_device(fdlb_ctx *c, double *fields);
+
+/* Checkpoint: the 33 distribution planes as 33 * ny * nx values of the storage type
+ * (float64 for FDLB_F64, float32 for FDLB_F32), plane q = 0 (rest particle) first, then
+ * q = 1 + 8 (k - 1) + (i - 1) for speed k and direction i pi/4.  `bytes` must equal
+ * fdlb_f_bytes(c).  fdlb_get_f syncs; fdlb_set_f copies then derives the pressure. */
+size_t fdlb_f_bytes(const fdlb_ctx *c);
+fdlb_status fdlb_get_f(fdlb_ctx *c, void *host, size_t bytes);
+fdlb_status fdlb_set_f(fdlb_ctx *c, const void *host, size_t bytes);
+
+/* Totals over the grid of n, n ux, n uy and the energy sum |v|^2 f / 2, and the sticky
+ * non-physical flag (0/1).  Deterministic (fixed reduction order).  Syncs. */
+fdlb_status fdlb_diag(fdlb_ctx *c, double sums[4], int32_t *nonphys);
+
+/* Steps taken since the last state was set. */
+int64_t fdlb_steps_done(const fdlb_ctx *c);
+
+void fdlb_destroy(fdlb_ctx *c);
+const char *fdlb_strerror(fdlb_status s);
+const char *fdlb_last_error(const fdlb_ctx *c);
+
+/* Tile shapes the step kernel is built for: writes up to `cap` (tx, ty) pairs and returns
+ * how many exist.  Shape id s (1-based) in fdlb_params.tile selects pair s - 1. */
+int32_t fdlb_tile_shapes(int32_t *tx_ty, int32_t cap);
+
+/* ---- Batched ensembles ------------------------------------------------------------- */
+/* k independent problems of possibly different size and parameters advanced together:
+ * every step is one launch over the tiles of all instances.  All instances must share
+ * the precision and the tile shape.  `arena` holds fdlb_batch_required_bytes bytes.
+ * fdlb_step, fdlb_diag (totals over all instances), fdlb_steps_done and fdlb_destroy
+ * accept batch contexts. */
+size_t fdlb_batch_required_bytes(int32_t k, const fdlb_params *p);
+fdlb_status fdlb_batch_create(int32_t k, const fdlb_params *p, void *stream, void *arena,
+                              size_t arena_bytes, fdlb_ctx **out);
+/* Instance i (0 <= i < k).  set_state marks the batch as set once every instance has
+ * been set at least once. */
+fdlb_status fdlb_batch_set_state(fdlb_ctx *c, int32_t i, const double *rho, const double *ux,
+                                 const double *uy, const double *T);
+fdlb_status fdlb_batch_get_moments(fdlb_ctx *c, int32_t i, double *rho, double *ux, double *uy,
+                                   double *T);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDLB_H */

@@ -1,0 +1,44 @@
+"""Builds libfdlb.so (HIP kernels + C interface) in place for gfx950 with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libfdlb.so")
+SOURCES = [os.path.join(CSRC, "fdlb_kernels.hip"), os.path.join(CSRC, "fdlb_api.cpp")]
+HEADERS = [os.path.join(CSRC, "fdlb_internal.h"), os.path.join(ROOT, "include", "fdlb.h")]
+
+# -ffp-contract=off: the float64 path reproduces a plain evaluation with no fused
+# multiply-add; the float32 path asks for its fused multiply-adds explicitly.
+# -packed-fp32-ops: no packed float32 instructions are generated.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+         "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument"]
+
+
+def hipcc():
+    return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def build(verbose: bool = False, extra=None) -> str:
+    out = LIB + ".tmp"
+    cmd = [hipcc()] + FLAGS + (extra or []) + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-x", "hip"] \
+        + SOURCES + ["-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("libfdlb build failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
+    if verbose:
+        print(" ".join(cmd))
+        if r.stderr.strip():
+            print(r.stderr)
+    os.replace(out, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
+    print(LIB)

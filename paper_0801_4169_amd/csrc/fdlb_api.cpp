@@ -1,0 +1,537 @@
+// fdlb_api.cpp -- host runtime behind the C interface of include/fdlb.h.
+//
+// A context owns: the per-instance descriptors (device copy), the tile table of the step
+// launch, the non-physical flag, reduction scratch and the captured step graphs.  The
+// distributions, pressures and wall rows live in the caller's arena.
+//
+// Model constants are computed here once in float64 with every expression written in the
+// order of the equations of the paper (compiled without contraction): the diagonal
+// component v_k * sqrt(2)/2, |v|^2 / 2, the weight-polynomial constants of Eq. (fk_eq1)
+// with the cyclic index of Eq. (kl_eq), and the line coefficients c/2, c^2/2 and
+// c (1 - c^2) / 12 of Eq. (dis_eq1) with c = v dt / dr (Eq. add3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fdlb.h"
+#include "fdlb_internal.h"
+
+using fdlb::Inst;
+using fdlb::Tile;
+
+namespace {
+
+constexpr double kHalfSqrt2 = 0.70710678118654757;  // nearest double to sqrt(2)/2
+constexpr int kGraphSteps = 32;                      // steps per captured graph (even)
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    int fpitch, ppitch, wlen;
+    int64_t fplane;
+    size_t esize;
+    size_t f_bytes, p_bytes, w_bytes, total;
+};
+
+Layout layout_of(const fdlb_params &p) {
+    Layout L{};
+    L.esize = p.precision == FDLB_F64 ? 8 : 4;
+    L.fpitch = round_up(p.nx, 32);
+    L.ppitch = round_up(p.nx, 32);
+    L.wlen = round_up(std::max(p.nx, p.ny), 32);
+    L.fplane = (int64_t)p.ny * L.fpitch;
+    L.f_bytes = align_up((size_t)fdlb::NQ * (size_t)L.fplane * L.esize, kAlign);
+    L.p_bytes = align_up((size_t)p.ny * L.ppitch * 8, kAlign);
+    L.w_bytes = align_up((size_t)4 * L.wlen * 8, kAlign);
+    L.total = 2 * (L.f_bytes + L.p_bytes + L.w_bytes);
+    return L;
+}
+
+bool finite_pos(double a) { return std::isfinite(a) && a > 0.0; }
+
+// 0 = valid
+int validate(const fdlb_params &p) {
+    if (p.nx < 1 || p.ny < 1) return 1;
+    if ((int64_t)p.nx * p.ny > (int64_t)1 << 30) return 1;
+    if (!finite_pos(p.dx) || !finite_pos(p.dy) || !finite_pos(p.dt) || !finite_pos(p.tau)) return 1;
+    if (!std::isfinite(p.lambda) || p.lambda < 0.0) return 1;
+    if (p.precision != FDLB_F64 && p.precision != FDLB_F32) return 1;
+    if (p.tile < 0 || p.tile > fdlb::kNumTileShapes) return 1;
+    double vmax = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        if (!finite_pos(p.v[k])) return 1;
+        for (int l = 0; l < k; ++l)
+            if (p.v[k] == p.v[l]) return 1;  // equal speeds make Eq. (fk_eq1) singular
+        vmax = std::max(vmax, p.v[k]);
+    }
+    // Courant numbers of Eq. (add3) must stay below one for the explicit stencil
+    if (!(vmax * p.dt / p.dx < 1.0) || !(vmax * p.dt / p.dy < 1.0)) return 1;
+    for (int s = 0; s < 4; ++s) {
+        const fdlb_bc &b = p.bc[s];
+        if (b.kind < FDLB_BC_PERIODIC || b.kind > FDLB_BC_WALL) return 1;
+        if (b.kind == FDLB_BC_WALL && ((s < 2 && p.nx < 2) || (s >= 2 && p.ny < 2))) return 1;
+        if (b.kind == FDLB_BC_DIRICHLET) {
+            if (!finite_pos(b.rho) || !finite_pos(b.T) || !std::isfinite(b.ux) || !std::isfinite(b.uy)) return 1;
+        }
+    }
+    if ((p.bc[0].kind == FDLB_BC_PERIODIC) != (p.bc[1].kind == FDLB_BC_PERIODIC)) return 1;
+    if ((p.bc[2].kind == FDLB_BC_PERIODIC) != (p.bc[3].kind == FDLB_BC_PERIODIC)) return 1;
+    return 0;
+}
+
+int default_shape(const fdlb_params &p) {
+    if (p.tile > 0) return p.tile - 1;
+    if (p.ny <= 4) return 1;  // 64 x 4: one tile spans a tube's whole height
+    return 0;                 // 32 x 8
+}
+
+void fill_constants(const fdlb_params &p, Inst &I) {
+    for (int k = 0; k < 4; ++k) {
+        const double v = p.v[k];
+        I.v[k] = v;
+        I.vs[k] = v * kHalfSqrt2;
+        I.eax[k] = 0.5 * (v * v);
+        I.edg[k] = 0.5 * (I.vs[k] * I.vs[k] + I.vs[k] * I.vs[k]);
+        const double vk2 = v * v;
+        const double a = p.v[(k + 1) % 4] * p.v[(k + 1) % 4];
+        const double b = p.v[(k + 2) % 4] * p.v[(k + 2) % 4];
+        const double d = p.v[(k + 3) % 4] * p.v[(k + 3) % 4];
+        I.FA[k] = 6.0 * (a + b + d);
+        I.FB[k] = a * b + b * d + d * a;
+        I.FC[k] = a * b * d / 4.0;
+        I.Fden[k] = vk2 * (vk2 - a) * (vk2 - b) * (vk2 - d);
+    }
+    for (int al = 0; al < 2; ++al) {
+        const double dr = al == 0 ? p.dx : p.dy;
+        for (int kind = 0; kind < 2; ++kind)
+            for (int k = 0; k < 4; ++k) {
+                const double mag = kind == 0 ? I.v[k] : I.vs[k];
+                const double c = mag * p.dt / dr;
+                I.k1[al][kind][k] = c / 2.0;
+                I.k2[al][kind][k] = c * c / 2.0;
+                I.k3[al][kind][k] = c * (1.0 - c * c) / 12.0;
+            }
+    }
+    I.dt = p.dt;
+    I.dx = p.dx;
+    I.dy = p.dy;
+    I.dtau = p.dt / p.tau;
+    I.lam = p.lambda;
+    for (int s = 0; s < 4; ++s) {
+        I.bc[s] = p.bc[s].kind;
+        I.bcstate[s][0] = p.bc[s].rho;
+        I.bcstate[s][1] = p.bc[s].ux;
+        I.bcstate[s][2] = p.bc[s].uy;
+        I.bcstate[s][3] = p.bc[s].T;
+        I.bcP[s] = 0.0;
+        for (int q = 0; q < fdlb::NQ; ++q) I.bcf[s][q] = 0.0;
+    }
+}
+
+}  // namespace
+
+struct fdlb_ctx {
+    int k = 0;
+    int prec = 0;
+    int shape = 0;
+    std::vector<fdlb_params> params;
+    std::vector<Layout> layouts;
+    std::vector<Inst> h_insts;
+    std::vector<int> tile_base;  // first tile of each instance
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    Inst *d_insts = nullptr;
+    Tile *d_tiles = nullptr;
+    int ntiles = 0;
+    int32_t *d_flag = nullptr;
+    double *d_partials = nullptr;
+    int nparts = 0;
+    double *d_sums = nullptr;
+    int half = 0;
+    int64_t steps = 0;
+    std::vector<char> is_set;
+    bool state_set = false;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+namespace {
+
+fdlb_status dev_fail(fdlb_ctx *c, hipError_t e, const char *what) {
+    if (c) c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return FDLB_EDEVICE;
+}
+
+#define HIPCHK(ctx, call)                                          \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return dev_fail((ctx), e_, #call);   \
+    } while (0)
+
+void release(fdlb_ctx *c) {
+    if (!c) return;
+    for (auto &g : c->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->d_insts) (void)hipFree(c->d_insts);
+    if (c->d_tiles) (void)hipFree(c->d_tiles);
+    if (c->d_flag) (void)hipFree(c->d_flag);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_sums) (void)hipFree(c->d_sums);
+    delete c;
+}
+
+fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, size_t bytes, fdlb_ctx **out) {
+    if (!out) return FDLB_EINVAL;
+    *out = nullptr;
+    if (k < 1 || !p || !arena) return FDLB_EINVAL;
+    if (reinterpret_cast<uintptr_t>(arena) % kAlign) return FDLB_EINVAL;
+    size_t need = 0;
+    for (int i = 0; i < k; ++i) {
+        if (validate(p[i])) return FDLB_EINVAL;
+        if (p[i].precision != p[0].precision || default_shape(p[i]) != default_shape(p[0])) return FDLB_EINVAL;
+        need += layout_of(p[i]).total;
+    }
+    if (bytes < need) return FDLB_EINVAL;
+
+    fdlb_ctx *c = new (std::nothrow) fdlb_ctx();
+    if (!c) return FDLB_ENOMEM;
+    c->k = k;
+    c->prec = p[0].precision;
+    c->shape = default_shape(p[0]);
+    c->stream = static_cast<hipStream_t>(stream);
+    c->params.assign(p, p + k);
+    c->is_set.assign(k, 0);
+    const int TX = fdlb::kTileShapes[c->shape].tx, TY = fdlb::kTileShapes[c->shape].ty;
+
+    hipError_t e;
+    if ((e = hipMalloc(&c->d_flag, sizeof(int32_t))) != hipSuccess) {
+        release(c);
+        return FDLB_ENOMEM;
+    }
+    std::vector<Tile> tiles;
+    char *base = static_cast<char *>(arena);
+    size_t off = 0;
+    c->h_insts.resize(k);
+    for (int i = 0; i < k; ++i) {
+        const Layout L = layout_of(p[i]);
+        c->layouts.push_back(L);
+        Inst &I = c->h_insts[i];
+        std::memset(&I, 0, sizeof(I));
+        I.nx = p[i].nx;
+        I.ny = p[i].ny;
+        I.fpitch = L.fpitch;
+        I.ppitch = L.ppitch;
+        I.fplane = L.fplane;
+        I.wlen = L.wlen;
+        I.prec = c->prec;
+        for (int h = 0; h < 2; ++h) {
+            I.f[h] = base + off;
+            off += L.f_bytes;
+        }
+        for (int h = 0; h < 2; ++h) {
+            I.P[h] = reinterpret_cast<double *>(base + off);
+            off += L.p_bytes;
+        }
+        for (int h = 0; h < 2; ++h) {
+            I.PW[h] = reinterpret_cast<double *>(base + off);
+            off += L.w_bytes;
+        }
+        I.flag = c->d_flag;
+        fill_constants(p[i], I);
+        c->tile_base.push_back((int)tiles.size());
+        for (int y0 = 0; y0 < p[i].ny; y0 += TY)
+            for (int x0 = 0; x0 < p[i].nx; x0 += TX) tiles.push_back(Tile{i, x0, y0, 0});
+    }
+    c->ntiles = (int)tiles.size();
+    int nparts = 0;
+    for (int i = 0; i < k; ++i) nparts += fdlb::diag_blocks(p[i].nx, p[i].ny);
+    c->nparts = nparts;
+    if (hipMalloc(&c->d_insts, sizeof(Inst) * k) != hipSuccess ||
+        hipMalloc(&c->d_tiles, sizeof(Tile) * tiles.size()) != hipSuccess ||
+        hipMalloc(&c->d_partials, sizeof(double) * 4 * (size_t)nparts) != hipSuccess ||
+        hipMalloc(&c->d_sums, sizeof(double) * 4) != hipSuccess) {
+        release(c);
+        return FDLB_ENOMEM;
+    }
+    if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+        fdlb_status s = dev_fail(c, e, "hipStreamCreateWithFlags");
+        release(c);
+        return s;
+    }
+    if ((e = hipMemcpyAsync(c->d_insts, c->h_insts.data(), sizeof(Inst) * k, hipMemcpyHostToDevice, c->stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice,
+                            c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream)) != hipSuccess) {
+        fdlb_status s = dev_fail(c, e, "upload");
+        release(c);
+        return s;
+    }
+    for (int i = 0; i < k; ++i)
+        if ((e = fdlb::launch_bc_setup(c->prec, c->d_insts, i, c->stream)) != hipSuccess) {
+            fdlb_status s = dev_fail(c, e, "bc_setup");
+            release(c);
+            return s;
+        }
+    // the descriptors and tile table come from host vectors: finish before they go away
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+        fdlb_status s = dev_fail(c, e, "hipStreamSynchronize");
+        release(c);
+        return s;
+    }
+    *out = c;
+    return FDLB_OK;
+}
+
+fdlb_status check_flag(fdlb_ctx *c) {
+    int32_t flag = 0;
+    HIPCHK(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return flag ? FDLB_ENONPHYS : FDLB_OK;
+}
+
+// Sets instance i from device fields (4 planes) into the current half.
+fdlb_status set_instance(fdlb_ctx *c, int i, const double *dfields) {
+    const fdlb_params &p = c->params[i];
+    HIPCHK(c, fdlb::launch_fill(c->prec, c->d_insts, i, p.nx, p.ny, dfields, c->half, c->stream));
+    HIPCHK(c, fdlb::launch_derive(c->prec, c->d_insts, i, p.nx, p.ny, c->half, c->stream));
+    c->is_set[i] = 1;
+    c->state_set = std::all_of(c->is_set.begin(), c->is_set.end(), [](char s) { return s != 0; });
+    c->steps = 0;
+    return FDLB_OK;
+}
+
+fdlb_status set_instance_host(fdlb_ctx *c, int i, const double *rho, const double *ux, const double *uy,
+                              const double *T) {
+    if (!rho || !ux || !uy || !T) return FDLB_EINVAL;
+    const fdlb_params &p = c->params[i];
+    const size_t n = (size_t)p.nx * p.ny;
+    // stage the fields in the other half's distribution planes (free until the next step)
+    double *stage = static_cast<double *>(c->h_insts[i].f[1 - c->half]);
+    const double *src[4] = {rho, ux, uy, T};
+    for (int a = 0; a < 4; ++a)
+        HIPCHK(c, hipMemcpyAsync(stage + a * n, src[a], n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
+    fdlb_status s = set_instance(c, i, stage);
+    if (s != FDLB_OK) return s;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FDLB_OK;
+}
+
+fdlb_status get_instance_host(fdlb_ctx *c, int i, double *rho, double *ux, double *uy, double *T) {
+    if (!rho || !ux || !uy || !T) return FDLB_EINVAL;
+    if (!c->state_set) return FDLB_ESTATE;
+    const fdlb_params &p = c->params[i];
+    const size_t n = (size_t)p.nx * p.ny;
+    double *stage = static_cast<double *>(c->h_insts[i].f[1 - c->half]);
+    HIPCHK(c, fdlb::launch_moments(c->prec, c->d_insts, i, p.nx, p.ny, c->half, stage, c->stream));
+    double *dst[4] = {rho, ux, uy, T};
+    for (int a = 0; a < 4; ++a)
+        HIPCHK(c, hipMemcpyAsync(dst[a], stage + a * n, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    return check_flag(c);
+}
+
+fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s) {
+    for (int64_t t = 0; t < n; ++t) {
+        HIPCHK(c, fdlb::launch_step(c->prec, c->shape, c->d_insts, c->d_tiles, c->ntiles, c->half, s));
+        c->half ^= 1;
+    }
+    return FDLB_OK;
+}
+
+// Graph of kGraphSteps steps starting from half h (kGraphSteps is even: ends in half h).
+fdlb_status ensure_graph(fdlb_ctx *c, int h) {
+    if (c->graph[h]) return FDLB_OK;
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    const int saved = c->half;
+    c->half = h;
+    fdlb_status s = launch_steps(c, kGraphSteps, c->cap_stream);
+    c->half = saved;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (s != FDLB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) return dev_fail(c, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->graph[h], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->graph[h] = nullptr;
+        return dev_fail(c, e, "hipGraphInstantiate");
+    }
+    return FDLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fdlb_required_bytes(const fdlb_params *p) {
+    if (!p || validate(*p)) return 0;
+    return layout_of(*p).total;
+}
+
+size_t fdlb_batch_required_bytes(int32_t k, const fdlb_params *p) {
+    if (k < 1 || !p) return 0;
+    size_t t = 0;
+    for (int i = 0; i < k; ++i) {
+        if (validate(p[i])) return 0;
+        t += layout_of(p[i]).total;
+    }
+    return t;
+}
+
+fdlb_status fdlb_create(const fdlb_params *p, void *stream, void *arena, size_t arena_bytes, fdlb_ctx **out) {
+    return build(1, p, stream, arena, arena_bytes, out);
+}
+
+fdlb_status fdlb_batch_create(int32_t k, const fdlb_params *p, void *stream, void *arena, size_t arena_bytes,
+                              fdlb_ctx **out) {
+    return build(k, p, stream, arena, arena_bytes, out);
+}
+
+fdlb_status fdlb_set_state(fdlb_ctx *c, const double *rho, const double *ux, const double *uy, const double *T) {
+    if (!c || c->k != 1) return FDLB_EINVAL;
+    return set_instance_host(c, 0, rho, ux, uy, T);
+}
+
+fdlb_status fdlb_set_state_device(fdlb_ctx *c, const double *fields) {
+    if (!c || c->k != 1 || !fields) return FDLB_EINVAL;
+    HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
+    return set_instance(c, 0, fields);
+}
+
+fdlb_status fdlb_batch_set_state(fdlb_ctx *c, int32_t i, const double *rho, const double *ux, const double *uy,
+                                 const double *T) {
+    if (!c || i < 0 || i >= c->k) return FDLB_EINVAL;
+    return set_instance_host(c, i, rho, ux, uy, T);
+}
+
+fdlb_status fdlb_step(fdlb_ctx *c, int64_t nsteps) {
+    if (!c || nsteps < 0) return FDLB_EINVAL;
+    if (!c->state_set) return FDLB_ESTATE;
+    int64_t left = nsteps;
+    while (left >= kGraphSteps) {
+        fdlb_status s = ensure_graph(c, c->half);
+        if (s != FDLB_OK) return s;
+        HIPCHK(c, hipGraphLaunch(c->graph[c->half], c->stream));
+        left -= kGraphSteps;
+    }
+    fdlb_status s = launch_steps(c, left, c->stream);
+    if (s != FDLB_OK) return s;
+    c->steps += nsteps;
+    return FDLB_OK;
+}
+
+fdlb_status fdlb_get_moments(fdlb_ctx *c, double *rho, double *ux, double *uy, double *T) {
+    if (!c || c->k != 1) return FDLB_EINVAL;
+    return get_instance_host(c, 0, rho, ux, uy, T);
+}
+
+fdlb_status fdlb_batch_get_moments(fdlb_ctx *c, int32_t i, double *rho, double *ux, double *uy, double *T) {
+    if (!c || i < 0 || i >= c->k) return FDLB_EINVAL;
+    return get_instance_host(c, i, rho, ux, uy, T);
+}
+
+fdlb_status fdlb_get_moments_device(fdlb_ctx *c, double *fields) {
+    if (!c || c->k != 1 || !fields) return FDLB_EINVAL;
+    if (!c->state_set) return FDLB_ESTATE;
+    const fdlb_params &p = c->params[0];
+    HIPCHK(c, fdlb::launch_moments(c->prec, c->d_insts, 0, p.nx, p.ny, c->half, fields, c->stream));
+    return FDLB_OK;
+}
+
+size_t fdlb_f_bytes(const fdlb_ctx *c) {
+    if (!c || c->k != 1) return 0;
+    const fdlb_params &p = c->params[0];
+    return (size_t)fdlb::NQ * p.nx * p.ny * c->layouts[0].esize;
+}
+
+fdlb_status fdlb_get_f(fdlb_ctx *c, void *host, size_t bytes) {
+    if (!c || c->k != 1 || !host || bytes != fdlb_f_bytes(c)) return FDLB_EINVAL;
+    if (!c->state_set) return FDLB_ESTATE;
+    const fdlb_params &p = c->params[0];
+    const Layout &L = c->layouts[0];
+    const char *src = static_cast<const char *>(c->h_insts[0].f[c->half]);
+    char *dst = static_cast<char *>(host);
+    const size_t row = (size_t)p.nx * L.esize;
+    for (int q = 0; q < fdlb::NQ; ++q)
+        HIPCHK(c, hipMemcpy2DAsync(dst + (size_t)q * p.ny * row, row, src + (size_t)q * L.fplane * L.esize,
+                                   (size_t)L.fpitch * L.esize, row, p.ny, hipMemcpyDeviceToHost, c->stream));
+    return check_flag(c);
+}
+
+fdlb_status fdlb_set_f(fdlb_ctx *c, const void *host, size_t bytes) {
+    if (!c || c->k != 1 || !host || bytes != fdlb_f_bytes(c)) return FDLB_EINVAL;
+    const fdlb_params &p = c->params[0];
+    const Layout &L = c->layouts[0];
+    char *dst = static_cast<char *>(c->h_insts[0].f[c->half]);
+    const char *src = static_cast<const char *>(host);
+    const size_t row = (size_t)p.nx * L.esize;
+    for (int q = 0; q < fdlb::NQ; ++q)
+        HIPCHK(c, hipMemcpy2DAsync(dst + (size_t)q * L.fplane * L.esize, (size_t)L.fpitch * L.esize,
+                                   src + (size_t)q * p.ny * row, row, row, p.ny, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
+    HIPCHK(c, fdlb::launch_derive(c->prec, c->d_insts, 0, p.nx, p.ny, c->half, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->is_set[0] = 1;
+    c->state_set = true;
+    c->steps = 0;
+    return FDLB_OK;
+}
+
+fdlb_status fdlb_diag(fdlb_ctx *c, double sums[4], int32_t *nonphys) {
+    if (!c || !sums) return FDLB_EINVAL;
+    if (!c->state_set) return FDLB_ESTATE;
+    int off = 0;
+    for (int i = 0; i < c->k; ++i) {
+        const fdlb_params &p = c->params[i];
+        HIPCHK(c, fdlb::launch_diag(c->prec, c->d_insts, i, p.nx, p.ny, c->half, c->d_partials, off, c->stream));
+        off += fdlb::diag_blocks(p.nx, p.ny);
+    }
+    HIPCHK(c, fdlb::launch_diag_final(c->d_partials, c->nparts, c->d_sums, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sums, c->d_sums, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    fdlb_status s = check_flag(c);
+    if (nonphys) *nonphys = s == FDLB_ENONPHYS ? 1 : 0;
+    return s == FDLB_ENONPHYS ? FDLB_OK : s;
+}
+
+int64_t fdlb_steps_done(const fdlb_ctx *c) { return c ? c->steps : 0; }
+
+void fdlb_destroy(fdlb_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+}
+
+const char *fdlb_strerror(fdlb_status s) {
+    switch (s) {
+    case FDLB_OK: return "ok";
+    case FDLB_EINVAL: return "invalid argument";
+    case FDLB_ENOMEM: return "out of memory";
+    case FDLB_EDEVICE: return "device error";
+    case FDLB_ENONPHYS: return "non-physical state (n <= 0, T <= 0, non-finite, or |u dt/dx| >= 1)";
+    case FDLB_ESTATE: return "no state set";
+    default: return "unknown status";
+    }
+}
+
+const char *fdlb_last_error(const fdlb_ctx *c) { return c ? c->err.c_str() : ""; }
+
+int32_t fdlb_tile_shapes(int32_t *tx_ty, int32_t cap) {
+    for (int s = 0; s < fdlb::kNumTileShapes && s < cap; ++s) {
+        tx_ty[2 * s] = fdlb::kTileShapes[s].tx;
+        tx_ty[2 * s + 1] = fdlb::kTileShapes[s].ty;
+    }
+    return fdlb::kNumTileShapes;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// fdlb_internal.h -- types shared by the HIP kernels and the host runtime of libfdlb.
+//
+// Layout in HBM (per instance, per ping-pong half h = 0, 1):
+//   f[h]  : 33 planes of ny rows x fpitch elements (float64 or float32), structure of
+//           arrays, x fastest; plane q = 0 is the rest particle, q = 1 + 8(k-1) + (i-1) the
+//           velocity of speed k and direction i pi/4 (Eq. dvm_eq_1).
+//   P[h]  : pressure n T of every cell, ny rows x ppitch float64.
+//   PW[h] : 4 rows of wlen float64, the pressure of the mirror image of the cells next to
+//           each reflecting side (x-, x+, y-, y+), read by the switching function.
+// The step reads half h and writes half 1 - h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdlb {
+
+constexpr int NQ = 33;
+constexpr int BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_DIRICHLET = 2, BC_WALL = 3;
+constexpr int PREC_F64 = 0, PREC_F32 = 1;
+
+// Per-instance constants and buffer pointers.  Lives in device memory and is read with
+// uniform (scalar) loads.  All constants are float64, computed on the host in a fixed
+// order (see fdlb_api.cpp).
+struct Inst {
+    int32_t nx, ny, fpitch, ppitch;
+    int64_t fplane;          // elements per f plane (ny * fpitch)
+    int32_t bc[4];           // x-, x+, y-, y+
+    int32_t wlen, prec;
+    void *f[2];
+    double *P[2];
+    double *PW[2];
+    int32_t *flag;           // sticky non-physical flag (shared by a batch)
+    int32_t *pad_ptr;
+    double v[4], vs[4];      // speeds and speed * sqrt(2)/2 (diagonal components)
+    double eax[4], edg[4];   // |v|^2 / 2 for axis and diagonal velocities
+    double FA[4], FB[4], FC[4], Fden[4]; // weight polynomial constants, Eq. (fk_eq1)
+    double k1[2][2][4], k2[2][2][4], k3[2][2][4]; // [alpha][axis=0, diag=1][speed], c >= 0
+    double dt, dx, dy, dtau, lam;
+    double bcstate[4][4];    // Dirichlet (rho, ux, uy, T) per side
+    double bcf[4][NQ];       // Dirichlet ghost vectors (values representable in storage)
+    double bcP[4];           // their pressures
+};
+
+struct Tile {
+    int32_t inst, x0, y0, pad;
+};
+
+struct TileShape {
+    int tx, ty;
+};
+
+// Tile shapes the step kernel is instantiated for (index = shape id - 1).
+constexpr TileShape kTileShapes[] = {{32, 8}, {64, 4}, {16, 16}, {64, 8}, {16, 4}, {128, 4}, {32, 4}};
+constexpr int kNumTileShapes = sizeof(kTileShapes) / sizeof(kTileShapes[0]);
+
+// Host-side launchers (fdlb_kernels.hip).  `insts` / `tiles` are device pointers.
+hipError_t launch_step(int prec, int shape, const Inst *insts, const Tile *tiles, int ntiles, int half,
+                       hipStream_t s);
+hipError_t launch_bc_setup(int prec, Inst *insts, int inst, hipStream_t s);
+hipError_t launch_fill(int prec, const Inst *insts, int inst, int nx, int ny, const double *fields, int half,
+                       hipStream_t s);
+hipError_t launch_derive(int prec, const Inst *insts, int inst, int nx, int ny, int half, hipStream_t s);
+hipError_t launch_moments(int prec, const Inst *insts, int inst, int nx, int ny, int half, double *out,
+                          hipStream_t s);
+hipError_t launch_diag(int prec, const Inst *insts, int inst, int nx, int ny, int half, double *partials,
+                       int npart_offset, hipStream_t s);
+hipError_t launch_diag_final(const double *partials, int nparts, double *sums, hipStream_t s);
+int diag_blocks(int nx, int ny);
+
+}  // namespace fdlb

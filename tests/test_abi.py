@@ -1,0 +1,89 @@
+"""The C interface: the library loads without a GPU and exports every function that
+include/fdlb.h declares; host-only calls (sizes, validation, strings) behave as documented.
+No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdlb.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdlb_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path_calls():
+    names = declared_functions()
+    for n in ("fdlb_create", "fdlb_set_state", "fdlb_step", "fdlb_get_moments", "fdlb_destroy",
+              "fdlb_batch_create", "fdlb_batch_set_state", "fdlb_batch_get_moments", "fdlb_get_f", "fdlb_set_f",
+              "fdlb_diag", "fdlb_required_bytes"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_0801_4169_amd import _binding as B
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+        assert n in B.EXPORTED, f"binding lacks {n}"
+
+
+def _sod_params(**kw):
+    import fdlb_inputs as fi
+    from paper_0801_4169_amd import _binding as B
+    p, _, _ = fi.sod_tube()
+    prm = B.make_params(p)
+    for k, v in kw.items():
+        setattr(prm, k, v)
+    return prm
+
+
+def test_required_bytes_layout():
+    from paper_0801_4169_amd import _binding as B
+    prm = _sod_params()
+    n64 = B.fdlb_required_bytes(prm)
+    prm32 = _sod_params(precision=B.FDLB_F32)
+    n32 = B.fdlb_required_bytes(prm32)
+    # two halves of 33 planes (pitch rounded to 32 cells) plus pressure rows
+    assert n64 >= 2 * 33 * 4 * 416 * 8 and n32 >= 2 * 33 * 4 * 416 * 4 and n32 < n64
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("dt", 0.0), ("tau", -1.0), ("dx", float("nan")),
+                                         ("dt", 1.0), ("precision", 7), ("tile", 99), ("lambda_", -1.0)])
+def test_invalid_parameters_are_rejected(field, value):
+    from paper_0801_4169_amd import _binding as B
+    assert B.fdlb_required_bytes(_sod_params(**{field: value})) == 0
+
+
+def test_unpaired_periodic_and_equal_speeds_are_rejected():
+    from paper_0801_4169_amd import _binding as B
+    prm = _sod_params()
+    prm.bc[2].kind = B.FDLB_BC_WALL  # y- wall with y+ periodic
+    assert B.fdlb_required_bytes(prm) == 0
+    prm = _sod_params()
+    prm.v[1] = prm.v[0]
+    assert B.fdlb_required_bytes(prm) == 0
+
+
+def test_create_rejects_short_or_misaligned_arena():
+    from paper_0801_4169_amd import _binding as B
+    prm = _sod_params()
+    n = B.fdlb_required_bytes(prm)
+    with pytest.raises(B.FdlbError) as e:
+        B.fdlb_create(prm, 0, 0x1000, n - 1)
+    assert e.value.status == B.FDLB_EINVAL
+    with pytest.raises(B.FdlbError):
+        B.fdlb_create(prm, 0, 0x1008, n)
+
+
+def test_strings_and_tile_shapes():
+    from paper_0801_4169_amd import _binding as B
+    assert "invalid" in B.fdlb_strerror(B.FDLB_EINVAL)
+    assert "non-physical" in B.fdlb_strerror(B.FDLB_ENONPHYS)
+    shapes = B.fdlb_tile_shapes()
+    assert (32, 8) in shapes and all(tx * ty <= 1024 for tx, ty in shapes)
