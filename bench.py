@@ -1,20 +1,24 @@
 """Benchmark of the FDLB hot path on one MI355X.
 
-Workload: the Mach-20 steady regular reflection (inflow (1, 20, 0, 0.5), 30-degree incident
-shock, reflecting wall at the bottom) on 8192 x 2048 cells, dx = dy = 2.5e-4, dt = 1e-6,
-tau = 2e-6, lambda = 2, 10000 steps by default.  A step is one fused kernel launch that
-advances all 33 distributions of every cell by Eq. (dis_eq1) of the paper.
+Workload (default): steady regular shock reflection on 8192 x 2048 cells, dx = dy = 2.5e-4,
+dt = 1e-6, tau = 2e-6, 10000 steps: freestream (1, 10, 0, 0.5), a 30-degree incident shock
+with the Rankine-Hugoniot post-shock state (gamma = 2) on the top side, reflecting wall at the
+bottom, outflow on the right, artificial-viscosity amplitude lambda = 20.  (The paper's
+Mach-20 inflow turns non-physical within a few steps with this scheme for every lambda, tau and
+dt tried; freestream Mach 10 with lambda = 20 runs the full 10000 steps.)  A step is one
+launch per tile kind that advances all 33 distributions of every cell by Eq. (dis_eq1).
 
-Reported: cell-updates per second of the float64 path (the headline `value`) and of the
-float32 path, the L1 difference between their final rho, u, T, the float64 step kernel's
-achieved HBM bandwidth against the MI355X peak, and the CPU oracle's rate on a short slice
-of the same workload.  Inputs are resident in HBM when the timed region starts; the timed
-region is K steps between HIP events on the solver's stream.
+Reported (one JSON line): cell-updates per second of the float64 path (`value`), the float32
+path and its L1 difference to float64 after the same steps, the 256-tube float32 ensemble,
+the roofline of the dominant kernel (interior tiles, timed alone with HIP events) against the
+MI355X HBM peak, HBM traffic from the committed counter summary when it matches the current
+kernel source, and the CPU oracle's rate on a bounded slice of the same grid.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
@@ -22,7 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-ALG_BYTES = {"f64": 2 * 33 * 8, "f32": 2 * 33 * 4}  # compulsory read + write of 33 planes per cell-update
+ALG_BYTES = {"f64": 2 * 33 * 8, "f32": 2 * 33 * 4}  # compulsory read + write of the 33 planes per cell-update
+KERNEL_SRC = os.path.join(ROOT, "paper_0801_4169_amd", "csrc", "fdlb_kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "step_interior_f64_reflection_8192x2048_counters.md")
 
 
 def parse():
@@ -34,9 +40,32 @@ def parse():
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--ny", type=int, default=2048)
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps of the CPU baseline slice (0: skip)")
-    ap.add_argument("--cpu-rows", type=int, default=512, help="rows of the CPU baseline slice")
+    ap.add_argument("--mach", type=float, default=10.0, help="freestream Mach number of the inflow")
+    ap.add_argument("--lam", type=float, default=20.0, help="artificial-viscosity amplitude lambda")
+    ap.add_argument("--ensemble-steps", type=int, default=5000, help="steps of the 256-tube ensemble (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps of the CPU baseline slice (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=256, help="rows of the CPU baseline slice")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this many MiB (calibrates the HBM "
+                         "byte counters of a profiler run against a kernel of known traffic)")
     return ap.parse_args()
+
+
+def src_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per interior-kernel launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    h = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]+)", text)
+    b = re.search(r"traffic bytes per launch: ([0-9.eE+]+)", text)
+    if not h or not b or h.group(1) != src_hash():
+        return None
+    return float(b.group(1))
 
 
 def timed_run(P, prob, fields, precision, steps, warmup, tile):
@@ -53,12 +82,16 @@ def timed_run(P, prob, fields, precision, steps, warmup, tile):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    # the dominant kernel (interior tiles) alone, HIP events on the same stream
+    k_ms = P.B.fdlb_time_kernel(s.ctx, 0, 50)
+    k_cells = P.B.fdlb_tile_cells(s.ctx, 0)
+    tiling = s.tiling
     m = s.moments(allow_nonphys=True)
     _, flag = s.diag()
     s.close()
     del s
     torch.cuda.empty_cache()
-    return ms, m, flag
+    return dict(ms=ms, moments=m, flag=flag, k_ms=k_ms, k_cells=k_cells, tiling=tiling)
 
 
 def l1_rel(a, b):
@@ -66,12 +99,44 @@ def l1_rel(a, b):
     return float(np.sum(np.abs(a - b)) / max(np.sum(np.abs(b)), 1e-300))
 
 
-def cpu_baseline(prob, fields, steps, rows):
-    """The float64 oracle on the first `rows` rows of the same grid (bottom wall, inflow,
-    outflow and top state as in the full problem), all host threads."""
-    import oracle
+def ensemble(P, steps):
     import numpy as np
-    nthr = os.cpu_count() or 1
+    import torch
+
+    import fdlb_inputs as fi
+    probs, _ = fi.ensemble_tubes()
+    b = P.BatchSolver([p for p, _ in probs], precision="f32")
+    for i, (p, flds) in enumerate(probs):
+        b.set_state(i, *flds)
+    b.step(20)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    physical = 0
+    for i in range(len(probs)):
+        r, u, w, T = b.moments(i, allow_nonphys=True)
+        physical += int(np.all(np.isfinite(T)) and np.all(r > 0) and np.all(T > 0))
+    cells = b.cells
+    out = {"workload": "ensemble_256_tubes_seed0", "dtype": "f32", "cells": cells, "steps": steps,
+           "ms_per_step": ms / steps, "value": cells * steps / (ms / 1e3) / 1e6, "unit": "Mcell-updates/s",
+           "hbm_frac": ALG_BYTES["f32"] * cells / (ms / steps / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "tiling": list(b.tiling), "instances_physical_at_end": physical}
+    b.close()
+    return out
+
+
+def cpu_baseline(prob, fields, steps, rows):
+    """The float64 oracle on the bottom `rows` rows of the same grid (same sides: reflecting
+    wall, inflow, outflow, top state), on the host threads the GPU job may use."""
+    import numpy as np
+
+    import oracle
+    nthr = max(1, min(16, os.cpu_count() or 1))
     sub = dict(prob)
     sub["ny"] = min(rows, prob["ny"])
     flds = tuple(np.ascontiguousarray(f[:sub["ny"]]) for f in fields)
@@ -82,8 +147,8 @@ def cpu_baseline(prob, fields, steps, rows):
     dt = time.perf_counter() - t
     cells = sub["nx"] * sub["ny"] * steps
     return {"value": cells / dt / 1e6, "unit": "Mcell-updates/s", "cores": nthr, "kind": "oracle",
-            "sample": f"{steps} steps of {sub['nx']}x{sub['ny']} (bottom rows of the benchmark grid), "
-                      f"{dt:.1f} s"}
+            "sample": f"{steps} steps of {sub['nx']}x{sub['ny']} (bottom rows of the benchmark grid, same "
+                      f"sides), {dt:.1f} s"}
 
 
 def main():
@@ -93,29 +158,31 @@ def main():
               "described in DESIGN.md and not built", file=sys.stderr)
         sys.exit(2)
     import torch
+
     import fdlb_inputs as fi
     import paper_0801_4169_amd as P
     if not torch.cuda.is_available():
         print("no GPU", file=sys.stderr)
         sys.exit(1)
 
-    prob, fields, _ = fi.reflection_8192x2048(nx=args.nx, ny=args.ny)
+    prob, fields, _ = fi.reflection_8192x2048(lam=args.lam, nx=args.nx, ny=args.ny, mach=args.mach)
     cells = prob["nx"] * prob["ny"]
     precs = ["f64", "f32"] if args.precision == "both" else [args.precision]
     res = {}
     for pr in precs:
         print(f"[bench] {pr}: {prob['nx']}x{prob['ny']}, {args.warmup} warmup + {args.steps} timed steps",
               file=sys.stderr, flush=True)
-        ms, m, flag = timed_run(P, prob, fields, pr, args.steps, args.warmup, args.tile)
-        rate = cells * args.steps / (ms / 1e3)
-        res[pr] = dict(ms=ms, moments=m, flag=flag, rate=rate)
-        print(f"[bench] {pr}: {ms / args.steps:.3f} ms/step, {rate / 1e9:.3f} Gcell-updates/s, "
-              f"non-physical={flag}", file=sys.stderr, flush=True)
+        r = timed_run(P, prob, fields, pr, args.steps, args.warmup, args.tile)
+        r["rate"] = cells * args.steps / (r["ms"] / 1e3)
+        res[pr] = r
+        print(f"[bench] {pr}: {r['ms'] / args.steps:.3f} ms/step, {r['rate'] / 1e9:.3f} Gcell-updates/s, "
+              f"interior kernel {r['k_ms']:.3f} ms, non-physical={r['flag']}", file=sys.stderr, flush=True)
 
     main_p = precs[0]
     r = res[main_p]
     ms_step = r["ms"] / args.steps
-    achieved = ALG_BYTES[main_p] * cells / (ms_step / 1e3) / 1e9
+    achieved = ALG_BYTES[main_p] * r["k_cells"] / (r["k_ms"] / 1e3) / 1e9
+    traffic = committed_traffic() if main_p == "f64" else None
     out = {
         "metric": "Mcell-updates/s FP32 vs FP64 at stated L1 error; % of HBM roofline",
         "value": r["rate"] / 1e6,
@@ -130,21 +197,39 @@ def main():
         "dtype": main_p,
         "data": "synthetic",
         "config": {"workload": prob["name"], "nx": prob["nx"], "ny": prob["ny"], "dx": prob["dx"],
-                   "dt": prob["dt"], "tau": prob["tau"], "lambda": prob["lam"], "storage": main_p},
+                   "dt": prob["dt"], "tau": prob["tau"], "lambda": prob["lam"], "storage": main_p,
+                   "tiling": list(r["tiling"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "fdlb::step_kernel", "alg_bytes_per_cell_update": ALG_BYTES[main_p]},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic / (r["k_ms"] / 1e3) / 1e9,
+                     "kernel": f"fdlb::step_kernel<{'double' if main_p == 'f64' else 'float'}, interior tiles>",
+                     "kernel_ms": r["k_ms"], "kernel_cells": r["k_cells"],
+                     "alg_bytes_per_cell_update": ALG_BYTES[main_p]},
         "nonphysical": bool(r["flag"]),
     }
     for pr in precs[1:]:
         o = res[pr]
         ent = {"value": o["rate"] / 1e6, "ms_per_step": o["ms"] / args.steps,
                "hbm_frac": ALG_BYTES[pr] * cells / (o["ms"] / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS,
-               "speedup_vs_f64": o["rate"] / res["f64"]["rate"], "nonphysical": bool(o["flag"])}
+               "kernel_ms": o["k_ms"],
+               "kernel_hbm_frac": ALG_BYTES[pr] * o["k_cells"] / (o["k_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+               "speedup_vs_f64": o["rate"] / res["f64"]["rate"], "nonphysical": bool(o["flag"]),
+               "tiling": list(o["tiling"])}
         if "f64" in res:
             a, b = o["moments"], res["f64"]["moments"]
-            ent["l1_vs_f64"] = {k: l1_rel(x, y) for k, x, y in zip(("rho", "ux", "uy", "T"), a, b)}
+            ent["l1_vs_f64_after_run"] = {k: l1_rel(x, y) for k, x, y in zip(("rho", "ux", "uy", "T"), a, b)}
         out[pr] = ent
+    if args.ensemble_steps > 0:
+        print("[bench] ensemble", file=sys.stderr, flush=True)
+        out["ensemble"] = ensemble(P, args.ensemble_steps)
+    if args.copy_probe_mib > 0:
+        a = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_mib"] = args.copy_probe_mib
+        del a, b
     if args.cpu_steps > 0:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, fields, args.cpu_steps, args.cpu_rows)

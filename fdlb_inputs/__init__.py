@@ -183,20 +183,28 @@ def regular_reflection(nx, ny, dx, dt, tau, lam, pre, post, beta_deg, name):
     return p, reflection_fields(nx, ny, dx, pre, post, beta_deg)
 
 
-def reflection_1024x256(lam=2.0):
-    """Normal Mach 10 shock at 29 degrees to the wall, 1024 x 256, 40000 steps."""
-    post, pre = oblique_shock_state((1.0, 1.0, 0.0, 0.5), mach_n=10.0, beta_deg=29.0)
+def reflection_1024x256(lam=2.0, mach=None):
+    """Shock incident at 29 degrees on a reflecting wall, 1024 x 256 cells, dx = 1e-3,
+    dt = 5e-6, tau = 1e-5, 40000 steps.  mach=None: the shock's normal Mach number is 10
+    (pre-shock T = 0.5, so u = 10 / sin 29deg); mach=M: freestream (1, M, 0, 0.5)."""
+    if mach is None:
+        post, pre = oblique_shock_state((1.0, 1.0, 0.0, 0.5), mach_n=10.0, beta_deg=29.0)
+        tag = "mn10"
+    else:
+        post, pre = oblique_shock_state((1.0, float(mach), 0.0, 0.5), beta_deg=29.0)
+        tag = f"m{mach:g}"
     p, f = regular_reflection(1024, 256, 1e-3, 5e-6, 1e-5, lam, pre, post, 29.0,
-                              "reflection_mn10_29deg_1024x256")
+                              f"reflection_{tag}_29deg_1024x256")
     return p, f, 40000
 
 
-def reflection_8192x2048(lam=2.0, nx=8192, ny=2048):
-    """Mach 20 inflow (1, 20, 0, 0.5) with the 30-degree incident shock of Sec. 5.2.1 on a
-    2.048 x 0.512 domain, 8192 x 2048 cells, 10000 steps."""
-    post, pre = oblique_shock_state(REFL_PRE, beta_deg=30.0)
+def reflection_8192x2048(lam=2.0, nx=8192, ny=2048, mach=20.0):
+    """Freestream (1, mach, 0, 0.5) with a 30-degree incident shock (Sec. 5.2.1 has
+    mach = 20), 2.048 x 0.512 domain, 8192 x 2048 cells, dx = 2.5e-4, dt = 1e-6,
+    tau = 2e-6, 10000 steps."""
+    post, pre = oblique_shock_state((1.0, float(mach), 0.0, 0.5), beta_deg=30.0)
     p, f = regular_reflection(nx, ny, 2.5e-4, 1e-6, 2e-6, lam, pre, post, 30.0,
-                              f"reflection_m20_30deg_{nx}x{ny}")
+                              f"reflection_m{mach:g}_30deg_{nx}x{ny}")
     return p, f, 10000
 
 

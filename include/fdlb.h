@@ -77,14 +77,14 @@ typedef struct {
 } fdlb_bc;
 
 typedef struct {
-    int32_t nx, ny;      /* cells; nx, ny >= 2 (and >= 5 if the side is not periodic) */
+    int32_t nx, ny;      /* cells; nx, ny >= 1, nx * ny <= 2^28, >= 2 across a wall */
     double dx, dy;       /* cell sizes, > 0 */
     double dt, tau;      /* time step and BGK relaxation time, > 0 (Eq. bgk_eq) */
     double lambda;       /* artificial-viscosity amplitude, >= 0 (Eq. add4) */
     double v[4];         /* speeds v1..v4 (Eq. dvm_eq_1); the paper uses 1, 1.92, 2.99, 4.49 */
     fdlb_bc bc[4];       /* x-, x+, y-, y+ */
     int32_t precision;   /* fdlb_precision */
-    int32_t tile;        /* tile shape id (fdlb_tile_shapes); 0 = library default */
+    int32_t tile;        /* tile shape id (fdlb_tile_shapes); 0 = library default (measured) */
 } fdlb_params;
 
 /* Bytes of device memory a context for these parameters borrows (both ping-pong halves:
@@ -148,6 +148,29 @@ const char *fdlb_last_error(const fdlb_ctx *c);
 /* Tile shapes the step kernel is built for: writes up to `cap` (tx, ty) pairs and returns
  * how many exist.  Shape id s (1-based) in fdlb_params.tile selects pair s - 1. */
 int32_t fdlb_tile_shapes(int32_t *tx_ty, int32_t cap);
+
+/* Tiling of the step launch: tile shape id (1-based, see fdlb_tile_shapes) and the width,
+ * in tiles, of the column groups the tiles are dispatched in (row by row inside a group;
+ * wider groups stream longer rows, narrower ones keep halo rows in L2).  Results do not
+ * depend on the tiling; only the speed does.  Syncs. */
+fdlb_status fdlb_set_tiling(fdlb_ctx *c, int32_t shape_id, int32_t group);
+fdlb_status fdlb_get_tiling(const fdlb_ctx *c, int32_t *shape_id, int32_t *group);
+
+/* Autotuner: times `trial_steps` steps for every (shape, group) candidate on the current
+ * state and keeps the fastest.  NULL / 0-length lists mean all shapes and groups
+ * {1, 4, 8, 16, 32}.  The trial steps do not advance the state (they read the current
+ * buffers and overwrite the spare ones).  best_ms (may be NULL) receives the best time per
+ * step.  Requires a state (FDLB_ESTATE).  Syncs. */
+fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape_ids, int32_t nshapes,
+                          const int32_t *groups, int32_t ngroups, float *best_ms);
+
+/* Measurement: the step is one launch per tile kind (0 interior tiles, 1 tiles spanning a
+ * periodic height of one tile, 2 tiles touching a side).  fdlb_tile_cells gives the grid
+ * cells a kind covers; fdlb_time_kernel times `launches` launches of one kind (-1: the
+ * whole step) with HIP events on the context's stream, without advancing the state (like
+ * the autotuner's trial steps).  Syncs. */
+int64_t fdlb_tile_cells(const fdlb_ctx *c, int32_t kind);
+fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float *ms_per_launch);
 
 /* ---- Batched ensembles ------------------------------------------------------------- */
 /* k independent problems of possibly different size and parameters advanced together:

@@ -28,7 +28,7 @@ NQ = 33
 
 def build(verbose=False):
     """Compile both oracle builds (float64 and __float128) in place."""
-    base = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    base = ["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
             "-fopenmp", "-Wall", "-Wno-unknown-pragmas"]
     for quad, lib in LIBS.items():
         cmd = base + (["-DORC_QUAD"] if quad else []) + [SRC, "-o", lib + ".tmp", "-lm"]

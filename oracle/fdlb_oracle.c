@@ -357,24 +357,26 @@ static void all_moments(grid_t *G, int nthreads)
 {
     const int nx = G->nx, ny = G->ny;
     (void)nthreads;
-#pragma omp parallel for num_threads(nthreads) schedule(static)
-    for (int y = -1; y <= ny; ++y) {
-        REAL mo[5];
-        if (y < 0 || y >= ny) {
-            for (int x = 0; x < nx; ++x) {
-                cell_moments(G, x, y, mo);
-                PI_(G, x, y) = mo[4];
-            }
-            continue;
-        }
+    /* interior cells plus the x ring (x = -1, nx) of every row */
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(static)
+    for (int y = 0; y < ny; ++y)
         for (int x = -1; x <= nx; ++x) {
+            REAL mo[5];
             cell_moments(G, x, y, mo);
             PI_(G, x, y) = mo[4];
             if (x >= 0 && x < nx)
                 for (int c = 0; c < 4; ++c)
                     G->mom[((size_t)c * ny + y) * nx + x] = mo[c];
         }
-    }
+    /* the y ring (y = -1, ny) */
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(static)
+    for (int r = 0; r < 2; ++r)
+        for (int x = 0; x < nx; ++x) {
+            REAL mo[5];
+            const int y = r == 0 ? -1 : ny;
+            cell_moments(G, x, y, mo);
+            PI_(G, x, y) = mo[4];
+        }
 }
 
 /* Switching function of Eq. (add4) and the line-IV coefficient theta |kappa| (1-|kappa|)/2
@@ -396,7 +398,7 @@ static void update(const grid_t *G, REAL *out, int nthreads)
     const int nx = G->nx, ny = G->ny;
     const int L = G->p.lines;
     (void)nthreads;
-#pragma omp parallel for num_threads(nthreads) schedule(static)
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(static)
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
             REAL n = G->mom[((size_t)0 * ny + y) * nx + x];

@@ -86,6 +86,21 @@ class Solver:
         return B.fdlb_diag(self.ctx)
 
     @property
+    def tiling(self):
+        """(tile shape id, dispatch-group width) of the step launch."""
+        return B.fdlb_get_tiling(self.ctx)
+
+    def set_tiling(self, shape_id, group):
+        B.fdlb_set_tiling(self.ctx, shape_id, group)
+
+    def autotune(self, trial_steps=20, shape_ids=(), groups=(), cache=None):
+        """Times the tiling candidates on the current state (which it leaves unchanged) and
+        keeps the fastest.  With ``cache`` (a JSON file path) a result for the same grid,
+        precision and device is reused instead of re-timed."""
+        return _autotune(self, trial_steps, shape_ids, groups, cache,
+                         key=f"{self.params.precision}:{self.nx}x{self.ny}")
+
+    @property
     def steps_done(self):
         return B.fdlb_steps_done(self.ctx)
 
@@ -99,6 +114,29 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def _autotune(solver, trial_steps, shape_ids, groups, cache, key):
+    import json
+    import os
+    torch = _torch()
+    key = f"{torch.cuda.get_device_name(solver.device)}:{key}"
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            table = json.load(fh)
+    if key in table:
+        sh, g = table[key]["shape"], table[key]["group"]
+        B.fdlb_set_tiling(solver.ctx, sh, g)
+        return sh, g, table[key]["ms"]
+    sh, g, ms = B.fdlb_autotune(solver.ctx, trial_steps, shape_ids, groups)
+    if cache:
+        table[key] = {"shape": sh, "group": g, "ms": ms}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return sh, g, ms
 
 
 class BatchSolver:
@@ -135,6 +173,19 @@ class BatchSolver:
 
     def diag(self):
         return B.fdlb_diag(self.ctx)
+
+    @property
+    def tiling(self):
+        return B.fdlb_get_tiling(self.ctx)
+
+    def set_tiling(self, shape_id, group):
+        B.fdlb_set_tiling(self.ctx, shape_id, group)
+
+    def autotune(self, trial_steps=20, shape_ids=(), groups=(), cache=None):
+        sizes = ",".join(f"{nx}x{ny}" for ny, nx in self.sizes)
+        import hashlib
+        key = f"{self.params[0].precision}:batch{len(self.sizes)}:" + hashlib.sha1(sizes.encode()).hexdigest()[:12]
+        return _autotune(self, trial_steps, shape_ids, groups, cache, key=key)
 
     def close(self):
         if getattr(self, "ctx", None):

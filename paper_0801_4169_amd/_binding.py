@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfdlb.so")
+# FDLB_LIB selects another build of the same library (for example one built with
+# different compile-time options); the default is the in-tree build.
+LIB_PATH = os.environ.get("FDLB_LIB") or os.path.join(HERE, "libfdlb.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libfdlb.so not built ({LIB_PATH}); run __graft_entry__.build() or "
@@ -70,6 +72,12 @@ _sigs = {
     "fdlb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fdlb_last_error": (ctypes.c_char_p, [_CTX]),
     "fdlb_tile_shapes": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    "fdlb_set_tiling": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32]),
+    "fdlb_get_tiling": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "fdlb_tile_cells": (ctypes.c_int64, [_CTX, ctypes.c_int32]),
+    "fdlb_time_kernel": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "fdlb_autotune": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
 }
 for _name, (_res, _args) in _sigs.items():
     _fn = getattr(_lib, _name)
@@ -213,6 +221,37 @@ def fdlb_steps_done(ctx):
 
 def fdlb_destroy(ctx):
     _lib.fdlb_destroy(ctx)
+
+
+def fdlb_set_tiling(ctx, shape_id, group):
+    _check(_lib.fdlb_set_tiling(ctx, int(shape_id), int(group)), ctx)
+
+
+def fdlb_get_tiling(ctx):
+    sh, g = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(_lib.fdlb_get_tiling(ctx, ctypes.byref(sh), ctypes.byref(g)), ctx)
+    return sh.value, g.value
+
+
+def fdlb_autotune(ctx, trial_steps, shape_ids=(), groups=()):
+    """Returns (shape_id, group, best ms per step) after tuning in place."""
+    sh = (ctypes.c_int32 * max(1, len(shape_ids)))(*shape_ids)
+    gr = (ctypes.c_int32 * max(1, len(groups)))(*groups)
+    best = ctypes.c_float(0)
+    _check(_lib.fdlb_autotune(ctx, int(trial_steps), sh, len(shape_ids), gr, len(groups), ctypes.byref(best)), ctx)
+    s, g = fdlb_get_tiling(ctx)
+    return s, g, best.value
+
+
+def fdlb_tile_cells(ctx, kind):
+    return int(_lib.fdlb_tile_cells(ctx, int(kind)))
+
+
+def fdlb_time_kernel(ctx, kind, launches):
+    """Milliseconds per launch of one tile kind (-1: whole step); the state is unchanged."""
+    ms = ctypes.c_float(0)
+    _check(_lib.fdlb_time_kernel(ctx, int(kind), int(launches), ctypes.byref(ms)), ctx)
+    return ms.value
 
 
 def fdlb_tile_shapes():

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -36,7 +37,7 @@ struct Layout {
     int fpitch, ppitch, wlen;
     int64_t fplane;
     size_t esize;
-    size_t f_bytes, p_bytes, w_bytes, total;
+    size_t f_bytes, p_bytes, m_bytes, w_bytes, total;
 };
 
 Layout layout_of(const fdlb_params &p) {
@@ -48,8 +49,9 @@ Layout layout_of(const fdlb_params &p) {
     L.fplane = (int64_t)p.ny * L.fpitch;
     L.f_bytes = align_up((size_t)fdlb::NQ * (size_t)L.fplane * L.esize, kAlign);
     L.p_bytes = align_up((size_t)p.ny * L.ppitch * 8, kAlign);
+    L.m_bytes = align_up((size_t)4 * p.ny * L.ppitch * 8, kAlign);
     L.w_bytes = align_up((size_t)4 * L.wlen * 8, kAlign);
-    L.total = 2 * (L.f_bytes + L.p_bytes + L.w_bytes);
+    L.total = 2 * (L.f_bytes + L.p_bytes + L.m_bytes + L.w_bytes);
     return L;
 }
 
@@ -58,7 +60,7 @@ bool finite_pos(double a) { return std::isfinite(a) && a > 0.0; }
 // 0 = valid
 int validate(const fdlb_params &p) {
     if (p.nx < 1 || p.ny < 1) return 1;
-    if ((int64_t)p.nx * p.ny > (int64_t)1 << 30) return 1;
+    if ((int64_t)p.nx * p.ny > (int64_t)1 << 28) return 1;  // a plane stays below 2 GiB
     if (!finite_pos(p.dx) || !finite_pos(p.dy) || !finite_pos(p.dt) || !finite_pos(p.tau)) return 1;
     if (!std::isfinite(p.lambda) || p.lambda < 0.0) return 1;
     if (p.precision != FDLB_F64 && p.precision != FDLB_F32) return 1;
@@ -85,10 +87,20 @@ int validate(const fdlb_params &p) {
     return 0;
 }
 
+// Tile columns per dispatch group, measured on the 8192 x 2048 grid (FDLB_TILE_GROUP
+// overrides).
+int default_group(int prec) {
+    const char *e = std::getenv("FDLB_TILE_GROUP");
+    if (e && std::atoi(e) > 0) return std::atoi(e);
+    return prec == FDLB_F64 ? 16 : 32;
+}
+
+// Tile shape (index into kTileShapes), measured: 64 x 8 for float64, 32 x 8 for float32;
+// 64 x 4 when the grid is four cells high (one tile spans a tube's periodic height).
 int default_shape(const fdlb_params &p) {
     if (p.tile > 0) return p.tile - 1;
-    if (p.ny <= 4) return 1;  // 64 x 4: one tile spans a tube's whole height
-    return 0;                 // 32 x 8
+    if (p.ny == 4) return 1;
+    return p.precision == FDLB_F64 ? 3 : 0;
 }
 
 void fill_constants(const fdlb_params &p, Inst &I) {
@@ -98,6 +110,8 @@ void fill_constants(const fdlb_params &p, Inst &I) {
         I.vs[k] = v * kHalfSqrt2;
         I.eax[k] = 0.5 * (v * v);
         I.edg[k] = 0.5 * (I.vs[k] * I.vs[k] + I.vs[k] * I.vs[k]);
+        I.vf[k] = (float)I.v[k];
+        I.vsf[k] = (float)I.vs[k];
         const double vk2 = v * v;
         const double a = p.v[(k + 1) % 4] * p.v[(k + 1) % 4];
         const double b = p.v[(k + 2) % 4] * p.v[(k + 2) % 4];
@@ -116,6 +130,10 @@ void fill_constants(const fdlb_params &p, Inst &I) {
                 I.k1[al][kind][k] = c / 2.0;
                 I.k2[al][kind][k] = c * c / 2.0;
                 I.k3[al][kind][k] = c * (1.0 - c * c) / 12.0;
+                I.kf[0][al][kind][k] = (float)I.k1[al][kind][k];
+                I.kf[1][al][kind][k] = (float)I.k2[al][kind][k];
+                I.kf[2][al][kind][k] = (float)I.k3[al][kind][k];
+                I.kkf[al][kind][k] = (float)(I.k1[al][kind][k] + 2.0 * I.k3[al][kind][k]);
             }
     }
     I.dt = p.dt;
@@ -140,15 +158,15 @@ struct fdlb_ctx {
     int k = 0;
     int prec = 0;
     int shape = 0;
+    int group = 1;
     std::vector<fdlb_params> params;
     std::vector<Layout> layouts;
     std::vector<Inst> h_insts;
-    std::vector<int> tile_base;  // first tile of each instance
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     Inst *d_insts = nullptr;
-    Tile *d_tiles = nullptr;
-    int ntiles = 0;
+    Tile *d_tiles[fdlb::kNumTileKinds] = {nullptr, nullptr, nullptr};
+    int ntiles[fdlb::kNumTileKinds] = {0, 0, 0};
     int32_t *d_flag = nullptr;
     double *d_partials = nullptr;
     int nparts = 0;
@@ -180,11 +198,55 @@ void release(fdlb_ctx *c) {
         if (g) (void)hipGraphExecDestroy(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->d_insts) (void)hipFree(c->d_insts);
-    if (c->d_tiles) (void)hipFree(c->d_tiles);
+    for (auto &t : c->d_tiles)
+        if (t) (void)hipFree(t);
     if (c->d_flag) (void)hipFree(c->d_flag);
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_sums) (void)hipFree(c->d_sums);
     delete c;
+}
+
+void drop_graphs(fdlb_ctx *c) {
+    for (auto &g : c->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// (Re)builds the tile tables for a tile shape and dispatch-group width.  Dispatch order:
+// groups of `group` tile columns, row by row inside a group, so a tile's x and y neighbours
+// are in flight at the same time on the same XCD and its halo rows are L2 hits (plain
+// row-major order re-reads every y halo from memory).  Synchronises the stream.
+fdlb_status set_tiles(fdlb_ctx *c, int shape, int group) {
+    const int TX = fdlb::kTileShapes[shape].tx, TY = fdlb::kTileShapes[shape].ty;
+    std::vector<Tile> tiles[fdlb::kNumTileKinds];
+    for (int i = 0; i < c->k; ++i) {
+        const fdlb_params &p = c->params[i];
+        const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
+        const int g = std::max(1, std::min(group, ntx));
+        for (int gx = 0; gx < ntx; gx += g)
+            for (int ty = 0; ty < nty; ++ty)
+                for (int tx = gx; tx < std::min(gx + g, ntx); ++tx) {
+                    const int x0 = tx * TX, y0 = ty * TY;
+                    tiles[fdlb::tile_kind(x0, y0, TX, TY, p.nx, p.ny, p.bc[2].kind)].push_back(Tile{i, x0, y0, 0});
+                }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd) {
+        if (c->d_tiles[kd]) (void)hipFree(c->d_tiles[kd]);
+        c->d_tiles[kd] = nullptr;
+        c->ntiles[kd] = (int)tiles[kd].size();
+        if (tiles[kd].empty()) continue;
+        if (hipMalloc(&c->d_tiles[kd], sizeof(Tile) * tiles[kd].size()) != hipSuccess) return FDLB_ENOMEM;
+        HIPCHK(c, hipMemcpyAsync(c->d_tiles[kd], tiles[kd].data(), sizeof(Tile) * tiles[kd].size(),
+                                 hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->shape = shape;
+    c->group = group;
+    drop_graphs(c);
+    return FDLB_OK;
 }
 
 fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, size_t bytes, fdlb_ctx **out) {
@@ -208,14 +270,13 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
     c->stream = static_cast<hipStream_t>(stream);
     c->params.assign(p, p + k);
     c->is_set.assign(k, 0);
-    const int TX = fdlb::kTileShapes[c->shape].tx, TY = fdlb::kTileShapes[c->shape].ty;
+    c->group = default_group(c->prec);
 
     hipError_t e;
     if ((e = hipMalloc(&c->d_flag, sizeof(int32_t))) != hipSuccess) {
         release(c);
         return FDLB_ENOMEM;
     }
-    std::vector<Tile> tiles;
     char *base = static_cast<char *>(arena);
     size_t off = 0;
     c->h_insts.resize(k);
@@ -240,21 +301,21 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
             off += L.p_bytes;
         }
         for (int h = 0; h < 2; ++h) {
+            I.M[h] = reinterpret_cast<double *>(base + off);
+            off += L.m_bytes;
+        }
+        I.mplane = (int64_t)p[i].ny * L.ppitch;
+        for (int h = 0; h < 2; ++h) {
             I.PW[h] = reinterpret_cast<double *>(base + off);
             off += L.w_bytes;
         }
         I.flag = c->d_flag;
         fill_constants(p[i], I);
-        c->tile_base.push_back((int)tiles.size());
-        for (int y0 = 0; y0 < p[i].ny; y0 += TY)
-            for (int x0 = 0; x0 < p[i].nx; x0 += TX) tiles.push_back(Tile{i, x0, y0, 0});
     }
-    c->ntiles = (int)tiles.size();
     int nparts = 0;
     for (int i = 0; i < k; ++i) nparts += fdlb::diag_blocks(p[i].nx, p[i].ny);
     c->nparts = nparts;
     if (hipMalloc(&c->d_insts, sizeof(Inst) * k) != hipSuccess ||
-        hipMalloc(&c->d_tiles, sizeof(Tile) * tiles.size()) != hipSuccess ||
         hipMalloc(&c->d_partials, sizeof(double) * 4 * (size_t)nparts) != hipSuccess ||
         hipMalloc(&c->d_sums, sizeof(double) * 4) != hipSuccess) {
         release(c);
@@ -267,8 +328,7 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
     }
     if ((e = hipMemcpyAsync(c->d_insts, c->h_insts.data(), sizeof(Inst) * k, hipMemcpyHostToDevice, c->stream)) !=
             hipSuccess ||
-        (e = hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice,
-                            c->stream)) != hipSuccess ||
+
         (e = hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream)) != hipSuccess) {
         fdlb_status s = dev_fail(c, e, "upload");
         release(c);
@@ -280,6 +340,13 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
             release(c);
             return s;
         }
+    {
+        fdlb_status ts = set_tiles(c, c->shape, c->group);
+        if (ts != FDLB_OK) {
+            release(c);
+            return ts;
+        }
+    }
     // the descriptors and tile table come from host vectors: finish before they go away
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) {
         fdlb_status s = dev_fail(c, e, "hipStreamSynchronize");
@@ -340,7 +407,9 @@ fdlb_status get_instance_host(fdlb_ctx *c, int i, double *rho, double *ux, doubl
 
 fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s) {
     for (int64_t t = 0; t < n; ++t) {
-        HIPCHK(c, fdlb::launch_step(c->prec, c->shape, c->d_insts, c->d_tiles, c->ntiles, c->half, s));
+        for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
+            if (c->ntiles[kd] > 0)
+                HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], c->half, s));
         c->half ^= 1;
     }
     return FDLB_OK;
@@ -505,6 +574,109 @@ fdlb_status fdlb_diag(fdlb_ctx *c, double sums[4], int32_t *nonphys) {
 }
 
 int64_t fdlb_steps_done(const fdlb_ctx *c) { return c ? c->steps : 0; }
+
+fdlb_status fdlb_set_tiling(fdlb_ctx *c, int32_t shape_id, int32_t group) {
+    if (!c || shape_id < 1 || shape_id > fdlb::kNumTileShapes || group < 1) return FDLB_EINVAL;
+    return set_tiles(c, shape_id - 1, group);
+}
+
+fdlb_status fdlb_get_tiling(const fdlb_ctx *c, int32_t *shape_id, int32_t *group) {
+    if (!c || !shape_id || !group) return FDLB_EINVAL;
+    *shape_id = c->shape + 1;
+    *group = c->group;
+    return FDLB_OK;
+}
+
+int64_t fdlb_tile_cells(const fdlb_ctx *c, int32_t kind) {
+    if (!c || kind < 0 || kind >= fdlb::kNumTileKinds) return 0;
+    // cells of the tiles of this kind that lie inside the grid
+    const int TX = fdlb::kTileShapes[c->shape].tx, TY = fdlb::kTileShapes[c->shape].ty;
+    int64_t cells = 0;
+    for (int i = 0; i < c->k; ++i) {
+        const fdlb_params &p = c->params[i];
+        for (int y0 = 0; y0 < p.ny; y0 += TY)
+            for (int x0 = 0; x0 < p.nx; x0 += TX)
+                if (fdlb::tile_kind(x0, y0, TX, TY, p.nx, p.ny, p.bc[2].kind) == kind)
+                    cells += (int64_t)std::min(TX, p.nx - x0) * std::min(TY, p.ny - y0);
+    }
+    return cells;
+}
+
+fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float *ms_per_launch) {
+    if (!c || !ms_per_launch || launches < 1 || kind < -1 || kind >= fdlb::kNumTileKinds) return FDLB_EINVAL;
+    if (!c->state_set) return FDLB_ESTATE;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const int h = c->half;
+    for (int w = 0; w < 2 + launches; ++w) {
+        if (w == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
+            if (c->ntiles[kd] > 0 && (kind < 0 || kd == kind))
+                HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], h,
+                                            c->stream));
+    }
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = ms / (float)launches;
+    return FDLB_OK;
+}
+
+fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape_ids, int32_t nshapes,
+                          const int32_t *groups, int32_t ngroups, float *best_ms) {
+    if (!c || trial_steps < 1 || nshapes < 0 || ngroups < 0) return FDLB_EINVAL;
+    if (!c->state_set) return FDLB_ESTATE;
+    std::vector<int> sh, gr;
+    for (int i = 0; i < nshapes; ++i) {
+        if (shape_ids[i] < 1 || shape_ids[i] > fdlb::kNumTileShapes) return FDLB_EINVAL;
+        sh.push_back(shape_ids[i] - 1);
+    }
+    for (int i = 0; i < ngroups; ++i) {
+        if (groups[i] < 1) return FDLB_EINVAL;
+        gr.push_back(groups[i]);
+    }
+    if (sh.empty())
+        for (int s = 0; s < fdlb::kNumTileShapes; ++s) sh.push_back(s);
+    if (gr.empty()) gr = {1, 4, 8, 16, 32};
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    float best = -1.0f;
+    int best_s = c->shape, best_g = c->group;
+    const int h = c->half;
+    for (int s : sh)
+        for (int g : gr) {
+            fdlb_status st = set_tiles(c, s, g);
+            if (st != FDLB_OK) return st;
+            // trial steps read the current half and write the other one without swapping:
+            // the state is left exactly as it was
+            for (int w = 0; w < 2 + trial_steps; ++w) {
+                if (w == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
+                for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
+                    if (c->ntiles[kd] > 0)
+                        HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd],
+                                                    h, c->stream));
+            }
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            ms /= (float)trial_steps;
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                best_s = s;
+                best_g = g;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_ms) *best_ms = best;
+    return set_tiles(c, best_s, best_g);
+}
 
 void fdlb_destroy(fdlb_ctx *c) {
     if (!c) return;

@@ -5,6 +5,8 @@
 //           arrays, x fastest; plane q = 0 is the rest particle, q = 1 + 8(k-1) + (i-1) the
 //           velocity of speed k and direction i pi/4 (Eq. dvm_eq_1).
 //   P[h]  : pressure n T of every cell, ny rows x ppitch float64.
+//   M[h]  : moments (n, ux, uy, T) of every cell, 4 planes of ny rows x ppitch float64,
+//           written by the step that produced the distributions and read by the next.
 //   PW[h] : 4 rows of wlen float64, the pressure of the mirror image of the cells next to
 //           each reflecting side (x-, x+, y-, y+), read by the switching function.
 // The step reads half h and writes half 1 - h.
@@ -29,7 +31,9 @@ struct Inst {
     int32_t wlen, prec;
     void *f[2];
     double *P[2];
+    double *M[2];
     double *PW[2];
+    int64_t mplane;          // elements per moment plane (ny * ppitch)
     int32_t *flag;           // sticky non-physical flag (shared by a batch)
     int32_t *pad_ptr;
     double v[4], vs[4];      // speeds and speed * sqrt(2)/2 (diagonal components)
@@ -37,6 +41,9 @@ struct Inst {
     double FA[4], FB[4], FC[4], Fden[4]; // weight polynomial constants, Eq. (fk_eq1)
     double k1[2][2][4], k2[2][2][4], k3[2][2][4]; // [alpha][axis=0, diag=1][speed], c >= 0
     double dt, dx, dy, dtau, lam;
+    float kf[3][2][2][4];    // float copies of k1, k2, k3 (float32 path)
+    float kkf[2][2][4];      // k1 + 2 k3, float32 path
+    float vf[4], vsf[4];     // float copies of v and vs
     double bcstate[4][4];    // Dirichlet (rho, ux, uy, T) per side
     double bcf[4][NQ];       // Dirichlet ghost vectors (values representable in storage)
     double bcP[4];           // their pressures
@@ -55,8 +62,11 @@ constexpr TileShape kTileShapes[] = {{32, 8}, {64, 4}, {16, 16}, {64, 8}, {16, 4
 constexpr int kNumTileShapes = sizeof(kTileShapes) / sizeof(kTileShapes[0]);
 
 // Host-side launchers (fdlb_kernels.hip).  `insts` / `tiles` are device pointers.
-hipError_t launch_step(int prec, int shape, const Inst *insts, const Tile *tiles, int ntiles, int half,
+// kind: 0 interior tiles, 1 tube tiles (periodic height == tile height), 2 edge tiles
+constexpr int kNumTileKinds = 3;
+hipError_t launch_step(int prec, int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
                        hipStream_t s);
+int tile_kind(int x0, int y0, int tx, int ty, int nx, int ny, int bc_y);
 hipError_t launch_bc_setup(int prec, Inst *insts, int inst, hipStream_t s);
 hipError_t launch_fill(int prec, const Inst *insts, int inst, int nx, int ny, const double *fields, int half,
                        hipStream_t s);

@@ -168,57 +168,221 @@ __device__ __forceinline__ A s_of(A mag, A ux, A uy) {
     }
 }
 
-// Arithmetic policy.  Exact: separate multiply and add (matches a plain evaluation with
-// no contraction).  Fused: fma.
-template <bool FUSE, class A>
-__device__ __forceinline__ A madd(A x, A k, A d) {
-    if constexpr (FUSE) {
-        return __builtin_fma(k, d, x);
-    } else {
-        const A t = k * d;
-        return x + t;
-    }
-}
-template <bool FUSE, class A>
-__device__ __forceinline__ A msub(A x, A k, A d) {
-    if constexpr (FUSE) {
-        return __builtin_fma(-k, d, x);
-    } else {
-        const A t = k * d;
-        return x - t;
-    }
-}
-template <bool FUSE>
-__device__ __forceinline__ float madd(float x, float k, float d) {
-    if constexpr (FUSE) return __builtin_fmaf(k, d, x); else { const float t = k * d; return x + t; }
-}
-template <bool FUSE>
-__device__ __forceinline__ float msub(float x, float k, float d) {
-    if constexpr (FUSE) return __builtin_fmaf(-k, d, x); else { const float t = k * d; return x - t; }
+// ------------------------------------------------------------------------------------
+// Float32 moments: float64 accumulation with fused multiply-adds (any order is fine for
+// the float32 path; the float64 path uses moments33 above).
+// ------------------------------------------------------------------------------------
+template <int MIR>
+__device__ __forceinline__ void moments33_fast(const Inst &I, const float (&f)[NQ], double &n, double &jx,
+                                               double &jy, double &E) {
+    n = 0.0;
+    jx = 0.0;
+    jy = 0.0;
+    E = 0.0;
+    static_for<0, NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int src = MIR == 0 ? q : MIR == 1 ? qmx(q) : qmy(q);
+        const double fq = static_cast<double>(f[src]);
+        n += fq;
+        if constexpr (q > 0) {
+            constexpr int k = qk(q);
+            const double mag = qdiag(q) ? I.vs[k] : I.v[k];
+            if constexpr (qsx(q) > 0) jx = __builtin_fma(mag, fq, jx);
+            if constexpr (qsx(q) < 0) jx = __builtin_fma(-mag, fq, jx);
+            if constexpr (qsy(q) > 0) jy = __builtin_fma(mag, fq, jy);
+            if constexpr (qsy(q) < 0) jy = __builtin_fma(-mag, fq, jy);
+            E = __builtin_fma(qdiag(q) ? I.edg[k] : I.eax[k], fq, E);
+        }
+    });
 }
 
-// Per-cell coefficients in the arithmetic type of the per-velocity work.
-template <class A>
-struct CellA {
-    A c0, c1, c2, c3, c4;
-    A nF[5];
-    A ux, uy, ax, ay, dtau;
+template <int MIR, class S>
+__device__ __forceinline__ void moments_of(const Inst &I, const S (&f)[NQ], double &n, double &jx, double &jy,
+                                           double &E) {
+    if constexpr (std::is_same<S, double>::value)
+        moments33<MIR>(I, f, n, jx, jy, E);
+    else
+        moments33_fast<MIR>(I, f, n, jx, jy, E);
+}
+
+// ------------------------------------------------------------------------------------
+// Float64 per-velocity update: Eq. (dis_eq1) in the fixed order (no contraction).
+// ------------------------------------------------------------------------------------
+struct CellD {
+    double c0, c1, c2, c3, c4;
+    double nF[5];
+    double ux, uy, ax, ay;
 };
 
-// One direction alpha of Eq. (dis_eq1): lines I, II, III, IV.  SGN is the sign of the
-// velocity component (0: only line IV, since c = 0 there).
-template <int SGN, bool FUSE, class A>
-__device__ __forceinline__ A lines_alpha(A fn, A f0, A fm2, A fm1, A fp1, A fp2, A k1, A k2, A k3, A av) {
-    const A d2 = fp1 - A(2) * f0 + fm1;
+// One direction alpha: lines I, II, III, IV added one by one.  SGN is the sign of the
+// velocity component; for a zero component the coefficients of lines I-III are zero and
+// only line IV remains.
+template <int SGN>
+__device__ __forceinline__ double lines_alpha(double fn, double f0, double fm2, double fm1, double fp1, double fp2,
+                                              double k1, double k2, double k3, double av) {
+    const double d2 = fp1 - 2.0 * f0 + fm1;
     if constexpr (SGN != 0) {
-        const A d1 = fp1 - fm1;
-        const A d3 = fp2 - A(2) * fp1 + A(2) * fm1 - fm2;
-        fn = SGN > 0 ? msub<FUSE>(fn, k1, d1) : madd<FUSE>(fn, k1, d1);  // line I
-        fn = madd<FUSE>(fn, k2, d2);                                     // line II
-        fn = SGN > 0 ? madd<FUSE>(fn, k3, d3) : msub<FUSE>(fn, k3, d3);  // line III
+        const double d1 = fp1 - fm1;
+        const double d3 = fp2 - 2.0 * fp1 + 2.0 * fm1 - fm2;
+        const double t1 = k1 * d1;
+        fn = SGN > 0 ? fn - t1 : fn + t1;  // line I
+        const double t2 = k2 * d2;
+        fn = fn + t2;  // line II
+        const double t3 = k3 * d3;
+        fn = SGN > 0 ? fn + t3 : fn - t3;  // line III
     }
-    fn = madd<FUSE>(fn, av, d2);  // line IV
+    const double t4 = av * d2;
+    return fn + t4;  // line IV
+}
+
+template <int Q>
+__device__ __forceinline__ double update_f64(const Inst &I, const CellD &c, double f0, double feq, double xm2,
+                                             double xm1, double xp1, double xp2, double ym2, double ym1, double yp1,
+                                             double yp2) {
+    constexpr int k = qk(Q), dg = qdiag(Q) ? 1 : 0;
+    double fn = f0;
+    if constexpr (qsx(Q) != 0)
+        fn = lines_alpha<qsx(Q)>(fn, f0, xm2, xm1, xp1, xp2, I.k1[0][dg][k], I.k2[0][dg][k], I.k3[0][dg][k], c.ax);
+    else
+        fn = lines_alpha<0>(fn, f0, xm2, xm1, xp1, xp2, 0.0, 0.0, 0.0, c.ax);
+    if constexpr (qsy(Q) != 0)
+        fn = lines_alpha<qsy(Q)>(fn, f0, ym2, ym1, yp1, yp2, I.k1[1][dg][k], I.k2[1][dg][k], I.k3[1][dg][k], c.ay);
+    else
+        fn = lines_alpha<0>(fn, f0, ym2, ym1, yp1, yp2, 0.0, 0.0, 0.0, c.ay);
+    const double t = I.dtau * (f0 - feq);  // BGK
+    return fn - t;
+}
+
+// Equilibrium of the opposite pair (q, q + 4): the powers of s = v . u are shared, the odd
+// ones change sign.  Same order as the plain evaluation c0 + c1 s + c2 s^2 + c3 s^3 + c4 s^4.
+template <int QA>
+__device__ __forceinline__ void feq_pair_f64(const Inst &I, const CellD &c, double &fa, double &fb) {
+    constexpr int k = qk(QA);
+    const double mag = qdiag(QA) ? I.vs[k] : I.v[k];
+    const double s = s_of<QA, double>(mag, c.ux, c.uy);
+    const double s2 = s * s;
+    const double s3 = s2 * s;
+    const double s4 = s3 * s;
+    const double t1 = c.c1 * s, t2 = c.c2 * s2, t3 = c.c3 * s3, t4 = c.c4 * s4;
+    fa = c.nF[k + 1] * (c.c0 + t1 + t2 + t3 + t4);
+    fb = c.nF[k + 1] * (c.c0 - t1 + t2 - t3 + t4);
+}
+
+// ------------------------------------------------------------------------------------
+// Float32 per-velocity update.  The same scheme, restated as weights on the five points of
+// each direction (line IV folded into line II), with fused multiply-adds:
+//   coefficient of f(+1) = K - (k1 + 2 k3), of f(-1) = K + (k1 + 2 k3), of f(+-2) = +-k3,
+//   of f(0) = 1 - dt/tau - 2 K_x - 2 K_y, with K = c^2/2 + theta |kappa| (1 - |kappa|)/2,
+// for a positive velocity component (the signs of k1, k3 flip with it).
+// ------------------------------------------------------------------------------------
+struct CellF {
+    float c0, c1, c2, c3, c4;
+    float nF[5];
+    float ux, uy, pA, pB;  // pA = ux + uy, pB = uy - ux
+    float ax, ay, omd, dtau;
+};
+
+template <int Q>
+__device__ __forceinline__ float update_f32(const Inst &I, const CellF &c, float f0, float feq, float xm2,
+                                            float xm1, float xp1, float xp2, float ym2, float ym1, float yp1,
+                                            float yp2) {
+    constexpr int k = qk(Q), dg = qdiag(Q) ? 1 : 0, sx = qsx(Q), sy = qsy(Q);
+    float Kx = c.ax, Ky = c.ay;
+    if constexpr (sx != 0) Kx = I.kf[1][0][dg][k] + c.ax;
+    if constexpr (sy != 0) Ky = I.kf[1][1][dg][k] + c.ay;
+    float fn = (c.omd - 2.0f * (Kx + Ky)) * f0;
+    fn = __builtin_fmaf(c.dtau, feq, fn);
+    if constexpr (sx != 0) {
+        const float kk = I.kkf[0][dg][k], k3 = I.kf[2][0][dg][k];
+        fn = __builtin_fmaf(sx > 0 ? Kx - kk : Kx + kk, xp1, fn);
+        fn = __builtin_fmaf(sx > 0 ? Kx + kk : Kx - kk, xm1, fn);
+        fn = __builtin_fmaf(sx > 0 ? k3 : -k3, xp2 - xm2, fn);
+    } else {
+        fn = __builtin_fmaf(Kx, xp1 + xm1, fn);
+    }
+    if constexpr (sy != 0) {
+        const float kk = I.kkf[1][dg][k], k3 = I.kf[2][1][dg][k];
+        fn = __builtin_fmaf(sy > 0 ? Ky - kk : Ky + kk, yp1, fn);
+        fn = __builtin_fmaf(sy > 0 ? Ky + kk : Ky - kk, ym1, fn);
+        fn = __builtin_fmaf(sy > 0 ? k3 : -k3, yp2 - ym2, fn);
+    } else {
+        fn = __builtin_fmaf(Ky, yp1 + ym1, fn);
+    }
     return fn;
+}
+
+template <int QA>
+__device__ __forceinline__ void feq_pair_f32(const Inst &I, const CellF &c, float &fa, float &fb) {
+    constexpr int i = qi(QA), k = qk(QA);
+    float s;
+    if constexpr (i == 1) s = I.vsf[k] * c.pA;
+    else if constexpr (i == 2) s = I.vf[k] * c.uy;
+    else if constexpr (i == 3) s = I.vsf[k] * c.pB;
+    else s = -(I.vf[k] * c.ux);
+    const float s2 = s * s;
+    const float ev = __builtin_fmaf(__builtin_fmaf(c.c4, s2, c.c2), s2, c.c0);
+    const float od = s * __builtin_fmaf(c.c3, s2, c.c1);
+    fa = c.nF[k + 1] * (ev + od);
+    fb = c.nF[k + 1] * (ev - od);
+}
+
+template <class S>
+struct CellOf;
+template <>
+struct CellOf<double> { using type = CellD; };
+template <>
+struct CellOf<float> { using type = CellF; };
+
+template <int Q, class S, class C>
+__device__ __forceinline__ S update_q(const Inst &I, const C &c, S f0, S feq, S xm2, S xm1, S xp1, S xp2, S ym2,
+                                      S ym1, S yp1, S yp2) {
+    if constexpr (std::is_same<S, double>::value)
+        return update_f64<Q>(I, c, f0, feq, xm2, xm1, xp1, xp2, ym2, ym1, yp1, yp2);
+    else
+        return update_f32<Q>(I, c, f0, feq, xm2, xm1, xp1, xp2, ym2, ym1, yp1, yp2);
+}
+
+template <int QA, class S, class C>
+__device__ __forceinline__ void feq_pair(const Inst &I, const C &c, S &fa, S &fb) {
+    if constexpr (std::is_same<S, double>::value)
+        feq_pair_f64<QA>(I, c, fa, fb);
+    else
+        feq_pair_f32<QA>(I, c, fa, fb);
+}
+
+__device__ __forceinline__ void make_cell(const Coef &C, double ux, double uy, double ax, double ay, double dtau,
+                                          CellD &c) {
+    c.c0 = C.c0;
+    c.c1 = C.c1;
+    c.c2 = C.c2;
+    c.c3 = C.c3;
+    c.c4 = C.c4;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) c.nF[k] = C.nF[k];
+    c.ux = ux;
+    c.uy = uy;
+    c.ax = ax;
+    c.ay = ay;
+    (void)dtau;
+}
+
+__device__ __forceinline__ void make_cell(const Coef &C, double ux, double uy, double ax, double ay, double dtau,
+                                          CellF &c) {
+    c.c0 = (float)C.c0;
+    c.c1 = (float)C.c1;
+    c.c2 = (float)C.c2;
+    c.c3 = (float)C.c3;
+    c.c4 = (float)C.c4;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) c.nF[k] = (float)C.nF[k];
+    c.ux = (float)ux;
+    c.uy = (float)uy;
+    c.pA = (float)(ux + uy);
+    c.pB = (float)(uy - ux);
+    c.ax = (float)ax;
+    c.ay = (float)ay;
+    c.omd = (float)(1.0 - dtau);
+    c.dtau = (float)dtau;
 }
 
 template <class S, int TX, int TY>
@@ -274,14 +438,6 @@ __device__ __forceinline__ Src map_cell(const Inst &I, int x, int y) {
     return s;
 }
 
-template <int Q, class S>
-__device__ __forceinline__ S load_src(const Inst &I, const S *__restrict__ fin, const Src &s, bool simple) {
-    if (simple) return fin[(size_t)Q * I.fplane + s.off];
-    if (s.dside >= 0) return static_cast<S>(I.bcf[s.dside][Q]);
-    const int qq = s.flip == 0 ? Q : s.flip == 1 ? qmx(Q) : s.flip == 2 ? qmy(Q) : qmx(qmy(Q));
-    return fin[(size_t)qq * I.fplane + s.off];
-}
-
 // Pressure of the neighbour (x, y) (at most one cell outside the grid).
 __device__ __forceinline__ double load_P(const Inst &I, const double *__restrict__ P,
                                          const double *__restrict__ PW, int x, int y) {
@@ -315,69 +471,129 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-// Pressure of the cell and of the mirror images next to reflecting sides, after the
-// cell's 33 values are final.
 template <class S>
-__device__ __forceinline__ void write_pressures(const Inst &I, const S (&f)[NQ], int x, int y, double *__restrict__ Pout,
-                                                double *__restrict__ PWout) {
+constexpr bool stream_moments();
+
+// Moments and pressure of the cell (from its final 33 values) and the pressure of the
+// mirror images next to reflecting sides.  Returns 1 if the cell's state is non-physical.
+template <class S>
+__device__ __forceinline__ int write_pressures(const Inst &I, const S (&f)[NQ], int x, int y,
+                                               double *__restrict__ Pout, double *__restrict__ Mout,
+                                               double *__restrict__ PWout) {
     double n, jx, jy, E, ux, uy, T, P;
-    moments33<0>(I, f, n, jx, jy, E);
+    moments_of<0>(I, f, n, jx, jy, E);
     primitive(n, jx, jy, E, ux, uy, T, P);
     Pout[y * I.ppitch + x] = P;
-    if (nonphysical(I, n, ux, uy, T)) *I.flag = 1;
+    if (stream_moments<S>()) {
+        Mout[y * I.ppitch + x] = n;
+        Mout[I.mplane + y * I.ppitch + x] = ux;
+        Mout[2 * I.mplane + y * I.ppitch + x] = uy;
+        Mout[3 * I.mplane + y * I.ppitch + x] = T;
+    }
+    const int bad = nonphysical(I, n, ux, uy, T) ? 1 : 0;
     if ((x == 0 && I.bc[0] == BC_WALL) || (x == I.nx - 1 && I.bc[1] == BC_WALL)) {
-        moments33<1>(I, f, n, jx, jy, E);
+        moments_of<1>(I, f, n, jx, jy, E);
         primitive(n, jx, jy, E, ux, uy, T, P);
         if (x == 0 && I.bc[0] == BC_WALL) PWout[0 * I.wlen + y] = P;
         if (x == I.nx - 1 && I.bc[1] == BC_WALL) PWout[1 * I.wlen + y] = P;
     }
     if ((y == 0 && I.bc[2] == BC_WALL) || (y == I.ny - 1 && I.bc[3] == BC_WALL)) {
-        moments33<2>(I, f, n, jx, jy, E);
+        moments_of<2>(I, f, n, jx, jy, E);
         primitive(n, jx, jy, E, ux, uy, T, P);
         if (y == 0 && I.bc[2] == BC_WALL) PWout[2 * I.wlen + x] = P;
         if (y == I.ny - 1 && I.bc[3] == BC_WALL) PWout[3 * I.wlen + x] = P;
     }
+    return bad;
 }
 
 // ------------------------------------------------------------------------------------
 // The fused step kernel.
+//
+// Tiles come in three kinds, each compiled as its own specialised body:
+//   INTERIOR: the tile and its two-cell halo lie inside the grid -- no boundary logic,
+//             every address is a per-plane base (scalar) plus a 32-bit offset;
+//   TUBE:     as INTERIOR along x, and the tile spans the whole periodic height of the grid
+//             (ny == TY): the y halo is the tile's own rows, written into LDS twice;
+//   EDGE:     everything else; halo cells are mapped through the side conditions.
 // ------------------------------------------------------------------------------------
-template <class S, class A, bool FUSE, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void step_kernel(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
-                                                      int ntiles, int half) {
-    constexpr int NT = TX * TY;
-    constexpr int NH = 4 * (TX + TY);
-    constexpr int NSLOT = (NH + NT - 1) / NT;
-    __shared__ StepSmem<S, TX, TY> sm;
+constexpr int MODE_INTERIOR = 0, MODE_TUBE = 1, MODE_EDGE = 2;
 
-    const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
+// Optimisation barrier for a uniform integer: after it the compiler cannot reuse values it
+// derived from `v` earlier, so per-stage plane offsets and constant loads happen inside each
+// stage instead of all being hoisted to the kernel entry (where they would not fit in the
+// scalar register file).  Emits no instruction.  Used on integers only: pointers keep the
+// global address space the compiler inferred for them.
+template <class T>
+__device__ __forceinline__ T opaque(T v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+// Distribution memory is addressed through explicit global (address space 1) pointers so
+// every access is a global_load / global_store with a scalar base and 32-bit offset.
+#define GLOBAL_AS __attribute__((address_space(1)))
+
+#ifndef FDLB_NT_STORE
+#define FDLB_NT_STORE 1  // new distributions are written with non-temporal stores (they are
+                         // not read again in the step; keeping them out of L2 leaves room for
+                         // the halo rows neighbouring tiles re-read)
+#endif
+
+// Store of a new distribution value (never read again within the step).
+template <class T>
+__device__ __forceinline__ void store_out(GLOBAL_AS T *p, T v) {
+#if FDLB_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+template <int Q, int MODE, class S>
+__device__ __forceinline__ S fetch(const Inst &I, const GLOBAL_AS char *fin, size_t pb, const Src &s) {
+    if constexpr (MODE != MODE_EDGE) {
+        return *reinterpret_cast<const GLOBAL_AS S *>(fin + (size_t)Q * pb + (uint32_t)s.off);
+    } else {
+        if (s.dside >= 0) return static_cast<S>(I.bcf[s.dside][Q]);
+        const int qq = s.flip == 0 ? Q : s.flip == 1 ? qmx(Q) : s.flip == 2 ? qmy(Q) : qmx(qmy(Q));
+        return reinterpret_cast<const GLOBAL_AS S *>(fin)[(size_t)qq * I.fplane + s.off];
+    }
+}
+
+template <class S, int TX, int TY, int MODE>
+__device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const Tile &tile, int half,
+                                          StepSmem<S, TX, TY> &sm) {
     const Inst &I = insts[tile.inst];
-    const S *__restrict__ fin = static_cast<const S *>(I.f[half]);
-    S *__restrict__ fout = static_cast<S *>(I.f[1 - half]);
-    const double *__restrict__ Pin = I.P[half];
-    const double *__restrict__ PWin = I.PW[half];
-    double *__restrict__ Pout = I.P[1 - half];
-    double *__restrict__ PWout = I.PW[1 - half];
+    constexpr int NT = TX * TY;
+    constexpr int H0 = MODE == MODE_TUBE ? 4 * TX : 0;  // the tube body loads only the x halo
+    constexpr int NHALL = 4 * (TX + TY);
+    constexpr int NSLOT = (NHALL - H0 + NT - 1) / NT;
+    constexpr int LW = TX + 4;
+    using Cell = typename CellOf<S>::type;
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int x = tile.x0 + tx, y = tile.y0 + ty;
     const int nx = I.nx, ny = I.ny;
-    const bool valid = x < nx && y < ny;
-    // a tile whose halo lies inside the grid needs no boundary mapping at all
-    const bool simple = tile.x0 >= 2 && tile.y0 >= 2 && tile.x0 + TX + 2 <= nx && tile.y0 + TY + 2 <= ny;
+    const bool valid = MODE != MODE_EDGE || (x < nx && y < ny);
+    const GLOBAL_AS char *fin = (const GLOBAL_AS char *)(I.f[half]);
+    GLOBAL_AS char *fout = (GLOBAL_AS char *)(I.f[1 - half]);
+    const size_t pb = (size_t)I.fplane * sizeof(S);
+    const double *__restrict__ Pin = I.P[half];
+    double *__restrict__ Pout = I.P[1 - half];
 
+    // offsets: bytes for INTERIOR / TUBE, elements (with mapping) for EDGE
     Src own;
-    if (simple) own = Src{y * I.fpitch + x, 0, -1};
+    if constexpr (MODE != MODE_EDGE) own = Src{(int)((y * I.fpitch + x) * (int)sizeof(S)), 0, -1};
     else own = map_cell(I, x, y);
     Src hs[NSLOT];
-    int hl[NSLOT];  // LDS position (ly * (TX + 4) + lx), -1 if the slot is unused
+    int hl[NSLOT];
 #pragma unroll
     for (int j = 0; j < NSLOT; ++j) {
-        const int hid = tid + j * NT;
+        const int hid = tid + j * NT + H0;
         hl[j] = -1;
         hs[j] = Src{0, 0, -1};
-        if (hid < NH) {
+        if (hid < NHALL) {
             int lx, ly;
             if (hid < 4 * TX) {
                 const int r = hid / TX;
@@ -389,38 +605,45 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(const Inst *__restrict__ i
                 ly = h2 % TY + 2;
                 lx = c < 2 ? c : TX + c;
             }
-            hl[j] = ly * (TX + 4) + lx;
+            hl[j] = ly * LW + lx;
             const int X = tile.x0 + lx - 2, Y = tile.y0 + ly - 2;
-            if (simple) hs[j] = Src{Y * I.fpitch + X, 0, -1};
+            if constexpr (MODE != MODE_EDGE) hs[j] = Src{(int)((Y * I.fpitch + X) * (int)sizeof(S)), 0, -1};
             else hs[j] = map_cell(I, X, Y);
         }
     }
 
-    // A1: own distributions
+    // A1: own distributions; the first halo stage is in flight during the moments
     S f[NQ];
     static_for<0, NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        f[q] = load_src<q>(I, fin, own, simple);
+        f[q] = fetch<q, MODE, S>(I, fin, pb, own);
     });
-    // halo of the first stage (rest particle) in flight during the moments
     S h0[NSLOT], h1[NSLOT];
 #pragma unroll
     for (int j = 0; j < NSLOT; ++j)
-        if (hl[j] >= 0) h0[j] = load_src<0>(I, fin, hs[j], simple);
+        if (hl[j] >= 0) h0[j] = fetch<0, MODE, S>(I, fin, pb, hs[j]);
 
     // A2: moments
     double n, jx, jy, E, ux, uy, T, P0;
-    moments33<0>(I, f, n, jx, jy, E);
+    moments_of<0>(I, f, n, jx, jy, E);
     primitive(n, jx, jy, E, ux, uy, T, P0);
 
-    // A3: switching function and line-IV coefficients
+    // A3: switching function and line-IV coefficients from the neighbours' pressure
     double Pxm, Pxp, Pym, Pyp;
-    if (simple) {
+    if constexpr (MODE == MODE_INTERIOR) {
+        const GLOBAL_AS double *pc = (const GLOBAL_AS double *)Pin + (y * I.ppitch + x);
+        Pxm = pc[-1];
+        Pxp = pc[1];
+        Pym = pc[-I.ppitch];
+        Pyp = pc[I.ppitch];
+    } else if constexpr (MODE == MODE_TUBE) {
+        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
         Pxm = Pin[y * I.ppitch + x - 1];
         Pxp = Pin[y * I.ppitch + x + 1];
-        Pym = Pin[(y - 1) * I.ppitch + x];
-        Pyp = Pin[(y + 1) * I.ppitch + x];
+        Pym = Pin[ym * I.ppitch + x];
+        Pyp = Pin[yp * I.ppitch + x];
     } else {
+        const double *PWin = I.PW[half];
         Pxm = load_P(I, Pin, PWin, x - 1, y);
         Pxp = load_P(I, Pin, PWin, x + 1, y);
         Pym = load_P(I, Pin, PWin, x, y - 1);
@@ -432,56 +655,38 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(const Inst *__restrict__ i
     // A4: equilibrium coefficients
     Coef C;
     equilibrium_coefs(I, n, ux, uy, T, C);
-    CellA<A> ca;
-    ca.c0 = static_cast<A>(C.c0);
-    ca.c1 = static_cast<A>(C.c1);
-    ca.c2 = static_cast<A>(C.c2);
-    ca.c3 = static_cast<A>(C.c3);
-    ca.c4 = static_cast<A>(C.c4);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) ca.nF[k] = static_cast<A>(C.nF[k]);
-    ca.ux = static_cast<A>(ux);
-    ca.uy = static_cast<A>(uy);
-    ca.ax = static_cast<A>(ax);
-    ca.ay = static_cast<A>(ay);
-    ca.dtau = static_cast<A>(I.dtau);
+    Cell cell;
+    make_cell(C, ux, uy, ax, ay, I.dtau, cell);
 
-    const int own_l = (ty + 2) * (TX + 4) + (tx + 2);
-    const size_t own_out = (size_t)y * I.fpitch + x;
+    const int own_l = (ty + 2) * LW + (tx + 2);
+    const uint32_t own_b = MODE != MODE_EDGE ? (uint32_t)own.off : (uint32_t)((y * I.fpitch + x) * (int)sizeof(S));
     int b = 0;
 
-    // A5: per velocity.  Stage 0 is the rest particle; stage 1 + 4k + j holds the pair of
-    // opposite velocities q = 1 + 8k + j and q + 4 (s and -s share their powers).
-    auto compute_q = [&](auto qc, const S *pl, A feq) {
+    auto put = [&](S *pl, S v) {
+        pl[own_l] = v;
+        if constexpr (MODE == MODE_TUBE) {
+            if (ty >= TY - 2) pl[own_l - TY * LW] = v;  // y = -2, -1 are rows ny - 2, ny - 1
+            if (ty < 2) pl[own_l + TY * LW] = v;        // y = ny, ny + 1 are rows 0, 1
+        }
+    };
+    // A5: one velocity from the LDS plane `pl`; A6: store it
+    auto compute = [&](auto qc, const Inst &Is, GLOBAL_AS char *fo, size_t pbs, const S *pl, S feq) {
         constexpr int q = decltype(qc)::value;
-        constexpr int k = qk(q);
-        constexpr int dg = qdiag(q) ? 1 : 0;
-        const A f0 = static_cast<A>(f[q]);
-        const A xm2 = static_cast<A>(pl[own_l - 2]), xm1 = static_cast<A>(pl[own_l - 1]);
-        const A xp1 = static_cast<A>(pl[own_l + 1]), xp2 = static_cast<A>(pl[own_l + 2]);
-        const A ym2 = static_cast<A>(pl[own_l - 2 * (TX + 4)]), ym1 = static_cast<A>(pl[own_l - (TX + 4)]);
-        const A yp1 = static_cast<A>(pl[own_l + (TX + 4)]), yp2 = static_cast<A>(pl[own_l + 2 * (TX + 4)]);
-        A fn = f0;
-        if constexpr (qsx(q) != 0)
-            fn = lines_alpha<qsx(q), FUSE, A>(fn, f0, xm2, xm1, xp1, xp2, static_cast<A>(I.k1[0][dg][k]),
-                                              static_cast<A>(I.k2[0][dg][k]), static_cast<A>(I.k3[0][dg][k]), ca.ax);
-        else
-            fn = lines_alpha<0, FUSE, A>(fn, f0, xm2, xm1, xp1, xp2, A(0), A(0), A(0), ca.ax);
-        if constexpr (qsy(q) != 0)
-            fn = lines_alpha<qsy(q), FUSE, A>(fn, f0, ym2, ym1, yp1, yp2, static_cast<A>(I.k1[1][dg][k]),
-                                              static_cast<A>(I.k2[1][dg][k]), static_cast<A>(I.k3[1][dg][k]), ca.ay);
-        else
-            fn = lines_alpha<0, FUSE, A>(fn, f0, ym2, ym1, yp1, yp2, A(0), A(0), A(0), ca.ay);
-        fn = msub<FUSE>(fn, ca.dtau, f0 - feq);  // BGK
-        const S out = static_cast<S>(fn);
-        if (valid) fout[(size_t)q * I.fplane + own_out] = out;
+        const S out = update_q<q, S>(Is, cell, f[q], feq, pl[own_l - 2], pl[own_l - 1], pl[own_l + 1],
+                                     pl[own_l + 2], pl[own_l - 2 * LW], pl[own_l - LW], pl[own_l + LW],
+                                     pl[own_l + 2 * LW]);
+        if (valid) store_out(reinterpret_cast<GLOBAL_AS S *>(fo + (size_t)q * pbs + own_b), out);
         f[q] = out;
     };
 
     // stage 0: rest particle
     {
+        const Inst &Is = insts[opaque(tile.inst)];
+        const GLOBAL_AS char *fi = fin;
+        GLOBAL_AS char *fo = fout;
+        const size_t pbs = opaque(pb);
         S *pl = &sm.buf[b][0][0][0];
-        pl[own_l] = f[0];
+        put(pl, f[0]);
 #pragma unroll
         for (int j = 0; j < NSLOT; ++j)
             if (hl[j] >= 0) pl[hl[j]] = h0[j];
@@ -489,27 +694,30 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(const Inst *__restrict__ i
 #pragma unroll
         for (int j = 0; j < NSLOT; ++j)
             if (hl[j] >= 0) {
-                h0[j] = load_src<1>(I, fin, hs[j], simple);
-                h1[j] = load_src<5>(I, fin, hs[j], simple);
+                h0[j] = fetch<1, MODE, S>(Is, fi, pbs, hs[j]);
+                h1[j] = fetch<5, MODE, S>(Is, fi, pbs, hs[j]);
             }
-        const A feq0 = ca.nF[0] * ca.c0;
-        compute_q(std::integral_constant<int, 0>{}, pl, feq0);
+        compute(std::integral_constant<int, 0>{}, Is, fo, pbs, pl, static_cast<S>(cell.nF[0] * cell.c0));
         b ^= 1;
     }
+    // stages 1..16: opposite pairs q = 1 + 8k + j and q + 4
     static_for<0, 16>([&](auto sc) {
         constexpr int st = decltype(sc)::value;
-        constexpr int k = st / 4;
-        constexpr int qa = 1 + 8 * k + (st % 4);
+        constexpr int qa = 1 + 8 * (st / 4) + (st % 4);
         constexpr int qb = qa + 4;
+        const Inst &Is = insts[opaque(tile.inst)];
+        const GLOBAL_AS char *fi = fin;
+        GLOBAL_AS char *fo = fout;
+        const size_t pbs = opaque(pb);
         S *pa = &sm.buf[b][0][0][0];
-        S *pb = &sm.buf[b][1][0][0];
-        pa[own_l] = f[qa];
-        pb[own_l] = f[qb];
+        S *pbuf = &sm.buf[b][1][0][0];
+        put(pa, f[qa]);
+        put(pbuf, f[qb]);
 #pragma unroll
         for (int j = 0; j < NSLOT; ++j)
             if (hl[j] >= 0) {
                 pa[hl[j]] = h0[j];
-                pb[hl[j]] = h1[j];
+                pbuf[hl[j]] = h1[j];
             }
         __syncthreads();
         if constexpr (st + 1 < 16) {
@@ -517,28 +725,277 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(const Inst *__restrict__ i
 #pragma unroll
             for (int j = 0; j < NSLOT; ++j)
                 if (hl[j] >= 0) {
-                    h0[j] = load_src<na>(I, fin, hs[j], simple);
-                    h1[j] = load_src<na + 4>(I, fin, hs[j], simple);
+                    h0[j] = fetch<na, MODE, S>(Is, fi, pbs, hs[j]);
+                    h1[j] = fetch<na + 4, MODE, S>(Is, fi, pbs, hs[j]);
                 }
         }
-        // equilibrium of the pair: the powers of s are shared, odd terms change sign
-        const A mag = static_cast<A>(qdiag(qa) ? I.vs[k] : I.v[k]);
-        const A s = s_of<qa, A>(mag, ca.ux, ca.uy);
-        const A s2 = s * s;
-        const A s3 = s2 * s;
-        const A s4 = s3 * s;
-        const A t1 = ca.c1 * s, t2 = ca.c2 * s2, t3 = ca.c3 * s3, t4 = ca.c4 * s4;
-        const A pp = ca.c0 + t1 + t2 + t3 + t4;
-        const A pm = ca.c0 - t1 + t2 - t3 + t4;
-        const A feqa = ca.nF[k + 1] * pp;
-        const A feqb = ca.nF[k + 1] * pm;
-        compute_q(std::integral_constant<int, qa>{}, pa, feqa);
-        compute_q(std::integral_constant<int, qb>{}, pb, feqb);
+        S fa, fb;
+        feq_pair<qa, S>(Is, cell, fa, fb);
+        compute(std::integral_constant<int, qa>{}, Is, fo, pbs, pa, fa);
+        compute(std::integral_constant<int, qb>{}, Is, fo, pbs, pbuf, fb);
         b ^= 1;
     });
 
-    // A6: pressure for the next step's switching function, wall images, flag
-    if (valid) write_pressures(I, f, x, y, Pout, PWout);
+    // A6: pressure for the next step's switching function, wall images, flag (one store
+    // per workgroup)
+    int bad = 0;
+    if constexpr (MODE == MODE_EDGE) {
+        if (valid) bad = write_pressures(I, f, x, y, Pout, I.M[1 - half], I.PW[1 - half]);
+    } else {
+        double n2, jx2, jy2, E2, ux2, uy2, T2, P2;
+        moments_of<0>(I, f, n2, jx2, jy2, E2);
+        primitive(n2, jx2, jy2, E2, ux2, uy2, T2, P2);
+        ((GLOBAL_AS double *)Pout)[y * I.ppitch + x] = P2;
+        bad = nonphysical(I, n2, ux2, uy2, T2) ? 1 : 0;
+    }
+    if (__syncthreads_or(bad) && tid == 0) *I.flag = 1;
+}
+
+// ------------------------------------------------------------------------------------
+// Stages: stage 0 is the rest particle; stage 1 + 4k + j holds the opposite pair
+// q = 1 + 8k + j and q + 4 (they share the powers of s in f^eq).
+// ------------------------------------------------------------------------------------
+constexpr int NSTAGE = 17;
+__host__ __device__ constexpr int stage_qa(int st) { return st == 0 ? 0 : 1 + 8 * ((st - 1) / 4) + ((st - 1) % 4); }
+__host__ __device__ constexpr int stage_qb(int st) { return st == 0 ? -1 : stage_qa(st) + 4; }
+
+// One term of the moments of Eqs. (n_eq), (nu_eq) and the energy, added to the running sums.
+// Float64: the same operation as one iteration of moments33 (so feeding the terms in
+// ascending q reproduces it exactly); float32 path: fused, any order.
+template <int Q, class S>
+__device__ __forceinline__ void acc_term(const Inst &I, S v, double &n, double &jx, double &jy, double &E) {
+    const double fq = static_cast<double>(v);
+    constexpr int k = qk(Q);
+    if constexpr (std::is_same<S, double>::value) {
+        n = n + fq;
+        if constexpr (Q > 0) {
+            const double mag = qdiag(Q) ? I.vs[k] : I.v[k];
+            if constexpr (qsx(Q) > 0) jx = jx + mag * fq;
+            if constexpr (qsx(Q) < 0) jx = jx - mag * fq;
+            if constexpr (qsy(Q) > 0) jy = jy + mag * fq;
+            if constexpr (qsy(Q) < 0) jy = jy - mag * fq;
+            const double e = qdiag(Q) ? I.edg[k] : I.eax[k];
+            E = E + e * fq;
+        }
+    } else {
+        n += fq;
+        if constexpr (Q > 0) {
+            const double mag = qdiag(Q) ? I.vs[k] : I.v[k];
+            if constexpr (qsx(Q) > 0) jx = __builtin_fma(mag, fq, jx);
+            if constexpr (qsx(Q) < 0) jx = __builtin_fma(-mag, fq, jx);
+            if constexpr (qsy(Q) > 0) jy = __builtin_fma(mag, fq, jy);
+            if constexpr (qsy(Q) < 0) jy = __builtin_fma(-mag, fq, jy);
+            E = __builtin_fma(qdiag(Q) ? I.edg[k] : I.eax[k], fq, E);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Streaming body for INTERIOR and TUBE tiles.  The cell's moments come from the moment
+// planes the previous step wrote (bit-identical to recomputing them), so the coefficients
+// are ready while the first planes are still in flight; the planes then stream through
+// the stages with a PD-deep prefetch, and the new moments are accumulated as the new
+// values appear, in ascending q (pair partners q + 4 are held until their turn).
+// ------------------------------------------------------------------------------------
+template <class S, int TX, int TY, int MODE, int PD>
+__device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts, const Tile &tile, int half,
+                                                 StepSmem<S, TX, TY> &sm) {
+    static_assert(MODE == MODE_INTERIOR || MODE == MODE_TUBE, "streaming body");
+    constexpr int NT = TX * TY;
+    constexpr int H0 = MODE == MODE_TUBE ? 4 * TX : 0;  // the tube body loads only the x halo
+    constexpr int NHALL = 4 * (TX + TY);
+    constexpr int NSLOT = (NHALL - H0 + NT - 1) / NT;
+    constexpr int LW = TX + 4;
+    using Cell = typename CellOf<S>::type;
+    const Inst &I = insts[tile.inst];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int x = tile.x0 + tx, y = tile.y0 + ty;
+    const int ny = I.ny;
+    const GLOBAL_AS char *fin = (const GLOBAL_AS char *)(I.f[half]);
+    GLOBAL_AS char *fout = (GLOBAL_AS char *)(I.f[1 - half]);
+    const size_t pb = (size_t)I.fplane * sizeof(S);
+
+    const Src own{(int)((y * I.fpitch + x) * (int)sizeof(S)), 0, -1};
+    Src hs[NSLOT];
+    int hl[NSLOT];
+#pragma unroll
+    for (int j = 0; j < NSLOT; ++j) {
+        const int hid = tid + j * NT + H0;
+        hl[j] = -1;
+        hs[j] = Src{0, 0, -1};
+        if (hid < NHALL) {
+            int lx, ly;
+            if (hid < 4 * TX) {
+                const int r = hid / TX;
+                lx = hid % TX + 2;
+                ly = r < 2 ? r : TY + r;
+            } else {
+                const int h2 = hid - 4 * TX;
+                const int c = h2 / TY;
+                ly = h2 % TY + 2;
+                lx = c < 2 ? c : TX + c;
+            }
+            hl[j] = ly * LW + lx;
+            const int X = tile.x0 + lx - 2, Y = tile.y0 + ly - 2;
+            hs[j] = Src{(int)((Y * I.fpitch + X) * (int)sizeof(S)), 0, -1};
+        }
+    }
+
+    // prefetch ring: own and halo values of the next PD stages
+    S po[PD][2];
+    S ph[PD][2][NSLOT];
+    auto load_stage = [&](auto stc, const Inst &Is, size_t pbs) {
+        constexpr int st = decltype(stc)::value;
+        constexpr int slot = st % PD, qa = stage_qa(st), qb = stage_qb(st);
+        po[slot][0] = fetch<qa, MODE, S>(Is, fin, pbs, own);
+        if constexpr (qb >= 0) po[slot][1] = fetch<qb, MODE, S>(Is, fin, pbs, own);
+#pragma unroll
+        for (int j = 0; j < NSLOT; ++j)
+            if (hl[j] >= 0) {
+                ph[slot][0][j] = fetch<qa, MODE, S>(Is, fin, pbs, hs[j]);
+                if constexpr (qb >= 0) ph[slot][1][j] = fetch<qb, MODE, S>(Is, fin, pbs, hs[j]);
+            }
+    };
+    static_for<0, PD>([&](auto stc) { load_stage(stc, I, pb); });
+
+    // A2: moments of the cell from the previous step; A3: switching function
+    const GLOBAL_AS double *Mc = (const GLOBAL_AS double *)I.M[half] + (y * I.ppitch + x);
+    const double n = Mc[0], ux = Mc[I.mplane], uy = Mc[2 * I.mplane], T = Mc[3 * I.mplane];
+    const double P0 = n * T;
+    double Pxm, Pxp, Pym, Pyp;
+    {
+        const GLOBAL_AS double *Pin = (const GLOBAL_AS double *)I.P[half];
+        const GLOBAL_AS double *pc = Pin + (y * I.ppitch + x);
+        Pxm = pc[-1];
+        Pxp = pc[1];
+        if constexpr (MODE == MODE_INTERIOR) {
+            Pym = pc[-I.ppitch];
+            Pyp = pc[I.ppitch];
+        } else {
+            Pym = Pin[(y == 0 ? ny - 1 : y - 1) * I.ppitch + x];
+            Pyp = Pin[(y == ny - 1 ? 0 : y + 1) * I.ppitch + x];
+        }
+    }
+    const double ax = av_coeff(I.lam, Pxm, P0, Pxp, ux, I.dt, I.dx);
+    const double ay = av_coeff(I.lam, Pym, P0, Pyp, uy, I.dt, I.dy);
+
+    // A4: equilibrium coefficients
+    Coef C;
+    equilibrium_coefs(I, n, ux, uy, T, C);
+    Cell cell;
+    make_cell(C, ux, uy, ax, ay, I.dtau, cell);
+
+    const int own_l = (ty + 2) * LW + (tx + 2);
+    const uint32_t own_b = (uint32_t)own.off;
+    auto put = [&](S *pl, S v) {
+        pl[own_l] = v;
+        if constexpr (MODE == MODE_TUBE) {
+            if (ty >= TY - 2) pl[own_l - TY * LW] = v;  // y = -2, -1 are rows ny - 2, ny - 1
+            if (ty < 2) pl[own_l + TY * LW] = v;        // y = ny, ny + 1 are rows 0, 1
+        }
+    };
+    auto update = [&](auto qc, const Inst &Is, const S *pl, S f0, S feq) {
+        constexpr int q = decltype(qc)::value;
+        return update_q<q, S>(Is, cell, f0, feq, pl[own_l - 2], pl[own_l - 1], pl[own_l + 1], pl[own_l + 2],
+                              pl[own_l - 2 * LW], pl[own_l - LW], pl[own_l + LW], pl[own_l + 2 * LW]);
+    };
+
+    double n2 = 0.0, jx2 = 0.0, jy2 = 0.0, E2 = 0.0;
+    S hold[3];
+    int b = 0;
+    static_for<0, NSTAGE>([&](auto stc) {
+        constexpr int st = decltype(stc)::value;
+        constexpr int slot = st % PD, qa = stage_qa(st), qb = stage_qb(st);
+        const Inst &Is = insts[opaque(tile.inst)];
+        const size_t pbs = opaque(pb);
+        S *pa = &sm.buf[b][0][0][0];
+        S *pbuf = &sm.buf[b][1][0][0];
+        const S fa0 = po[slot][0];
+        S fb0 = fa0;
+        put(pa, fa0);
+        if constexpr (qb >= 0) {
+            fb0 = po[slot][1];
+            put(pbuf, fb0);
+        }
+#pragma unroll
+        for (int j = 0; j < NSLOT; ++j)
+            if (hl[j] >= 0) {
+                pa[hl[j]] = ph[slot][0][j];
+                if constexpr (qb >= 0) pbuf[hl[j]] = ph[slot][1][j];
+            }
+        __syncthreads();
+        if constexpr (st + PD < NSTAGE) load_stage(std::integral_constant<int, st + PD>{}, Is, pbs);
+        if constexpr (qb < 0) {
+            const S fn = update(std::integral_constant<int, 0>{}, Is, pa, fa0, static_cast<S>(cell.nF[0] * cell.c0));
+            store_out(reinterpret_cast<GLOBAL_AS S *>(fout + own_b), fn);
+            acc_term<0>(Is, fn, n2, jx2, jy2, E2);
+        } else {
+            S fea, feb;
+            feq_pair<qa, S>(Is, cell, fea, feb);
+            const S fna = update(std::integral_constant<int, qa>{}, Is, pa, fa0, fea);
+            const S fnb = update(std::integral_constant<int, qb>{}, Is, pbuf, fb0, feb);
+            store_out(reinterpret_cast<GLOBAL_AS S *>(fout + (size_t)qa * pbs + own_b), fna);
+            store_out(reinterpret_cast<GLOBAL_AS S *>(fout + (size_t)qb * pbs + own_b), fnb);
+            // ascending q within the speed group: 1..4 as they come, 5..7 held, then 8
+            constexpr int j = (st - 1) % 4;
+            acc_term<qa>(Is, fna, n2, jx2, jy2, E2);
+            if constexpr (j < 3) {
+                hold[j] = fnb;
+            } else {
+                acc_term<qa + 1>(Is, hold[0], n2, jx2, jy2, E2);
+                acc_term<qa + 2>(Is, hold[1], n2, jx2, jy2, E2);
+                acc_term<qa + 3>(Is, hold[2], n2, jx2, jy2, E2);
+                acc_term<qb>(Is, fnb, n2, jx2, jy2, E2);
+            }
+        }
+        b ^= 1;
+    });
+
+    // A6: moments and pressure for the next step, flag (one store per workgroup)
+    double ux2, uy2, T2, P2;
+    primitive(n2, jx2, jy2, E2, ux2, uy2, T2, P2);
+    GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[1 - half] + (y * I.ppitch + x);
+    Mo[0] = n2;
+    Mo[I.mplane] = ux2;
+    Mo[2 * I.mplane] = uy2;
+    Mo[3 * I.mplane] = T2;
+    ((GLOBAL_AS double *)I.P[1 - half])[y * I.ppitch + x] = P2;
+    const int bad = nonphysical(I, n2, ux2, uy2, T2) ? 1 : 0;
+    if (__syncthreads_or(bad) && tid == 0) *I.flag = 1;
+}
+
+#ifndef FDLB_PREFETCH
+#define FDLB_PREFETCH 2  // stages of look-ahead of the streaming body
+#endif
+// Interior body per precision (measured): float64 streams the planes and reads the
+// moments the previous step stored; float32 keeps the cell's 33 values in registers and
+// recomputes its moments (its extra moment traffic would cost more than the recompute).
+// FDLB_STREAM = 0 / 1 forces one body for both precisions.
+#ifndef FDLB_STREAM
+#define FDLB_STREAM -1
+#endif
+template <class S>
+constexpr bool use_stream() {
+    return FDLB_STREAM < 0 ? std::is_same<S, double>::value : FDLB_STREAM != 0;
+}
+template <class S>
+constexpr bool stream_moments() {
+    return use_stream<S>();
+}
+
+// One kernel per tile kind, so the common interior kernel gets its own (small) register
+// allocation; the host splits the tile table by kind (same rule as tile_kind below).
+template <class S, int TX, int TY, int MODE>
+__global__ __launch_bounds__(TX *TY) void step_kernel(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
+                                                      int ntiles, int half) {
+    __shared__ StepSmem<S, TX, TY> sm;
+    const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
+    if constexpr (MODE == MODE_EDGE || !use_stream<S>())
+        step_body<S, TX, TY, MODE>(insts, tile, half, sm);
+    else
+        step_body_stream<S, TX, TY, MODE, FDLB_PREFETCH>(insts, tile, half, sm);
 }
 
 // ------------------------------------------------------------------------------------
@@ -580,7 +1037,7 @@ __global__ __launch_bounds__(256) void derive_kernel(const Inst *__restrict__ in
     S f[NQ];
     const size_t off = (size_t)y * I.fpitch + x;
     static_for<0, NQ>([&](auto qc) { f[decltype(qc)::value] = fin[(size_t)decltype(qc)::value * I.fplane + off]; });
-    write_pressures(I, f, x, y, I.P[half], I.PW[half]);
+    if (write_pressures(I, f, x, y, I.P[half], I.M[half], I.PW[half])) *I.flag = 1;
 }
 
 // Dirichlet ghost vectors f^eq(state) rounded to storage, and their pressures.
@@ -610,7 +1067,7 @@ __global__ void bc_setup_kernel(Inst *insts, int inst) {
     });
     static_for<0, NQ>([&](auto qc) { I.bcf[side][decltype(qc)::value] = to_d(g[decltype(qc)::value]); });
     double m, jx, jy, E, vx, vy, T2, P;
-    moments33<0>(I, g, m, jx, jy, E);
+    moments_of<0>(I, g, m, jx, jy, E);
     primitive(m, jx, jy, E, vx, vy, T2, P);
     I.bcP[side] = P;
 }
@@ -626,7 +1083,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const Inst *__restrict__ i
     const size_t off = (size_t)y * I.fpitch + x;
     static_for<0, NQ>([&](auto qc) { f[decltype(qc)::value] = fin[(size_t)decltype(qc)::value * I.fplane + off]; });
     double n, jx, jy, E, ux, uy, T, P;
-    moments33<0>(I, f, n, jx, jy, E);
+    moments_of<0>(I, f, n, jx, jy, E);
     primitive(n, jx, jy, E, ux, uy, T, P);
     const size_t c = (size_t)y * I.nx + x, plane = (size_t)I.nx * I.ny;
     out[c] = n;
@@ -650,7 +1107,7 @@ __global__ __launch_bounds__(256) void diag_kernel(const Inst *__restrict__ inst
         S f[NQ];
         const size_t off = (size_t)y * I.fpitch + x;
         static_for<0, NQ>([&](auto qc) { f[decltype(qc)::value] = fin[(size_t)decltype(qc)::value * I.fplane + off]; });
-        moments33<0>(I, f, v[0], v[1], v[2], v[3]);
+        moments_of<0>(I, f, v[0], v[1], v[2], v[3]);
         double ux, uy, T, P;
         primitive(v[0], v[1], v[2], v[3], ux, uy, T, P);
         if (nonphysical(I, v[0], ux, uy, T)) *I.flag = 1;
@@ -665,45 +1122,70 @@ __global__ __launch_bounds__(256) void diag_kernel(const Inst *__restrict__ inst
     if (threadIdx.x < 4) partials[4 * (long)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void diag_final_kernel(const double *__restrict__ partials, int nparts, double *__restrict__ sums) {
-    const int c = threadIdx.x;
-    if (c >= 4) return;
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s = s + partials[4 * (long)i + c];
-    sums[c] = s;
+__global__ __launch_bounds__(kDiagBlock) void diag_final_kernel(const double *__restrict__ partials, int nparts,
+                                                                double *__restrict__ sums) {
+    // each thread sums a fixed strided subset in order, then a fixed tree: deterministic
+    __shared__ double red[4][kDiagBlock];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nparts; i += kDiagBlock)
+        for (int c = 0; c < 4; ++c) v[c] = v[c] + partials[4 * (long)i + c];
+    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int w = kDiagBlock / 2; w > 0; w /= 2) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = red[c][threadIdx.x] + red[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) sums[threadIdx.x] = red[threadIdx.x][0];
 }
 
 // ------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------
-template <class S, class A, bool FUSE, int SHAPE>
-static hipError_t launch_step_t(const Inst *insts, const Tile *tiles, int ntiles, int half, hipStream_t s) {
+template <class S, int SHAPE, int MODE>
+static hipError_t launch_step_m(const Inst *insts, const Tile *tiles, int ntiles, int half, hipStream_t s) {
     constexpr int TX = kTileShapes[SHAPE].tx, TY = kTileShapes[SHAPE].ty;
-    hipLaunchKernelGGL((step_kernel<S, A, FUSE, TX, TY>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles, ntiles,
+    hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles, ntiles,
                        half);
     return hipGetLastError();
 }
 
-template <class S, class A, bool FUSE>
-static hipError_t launch_step_p(int shape, const Inst *insts, const Tile *tiles, int ntiles, int half,
+template <class S, int SHAPE>
+static hipError_t launch_step_t(int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
+                                hipStream_t s) {
+    if (kind == MODE_INTERIOR) return launch_step_m<S, SHAPE, MODE_INTERIOR>(insts, tiles, ntiles, half, s);
+    if (kind == MODE_TUBE) return launch_step_m<S, SHAPE, MODE_TUBE>(insts, tiles, ntiles, half, s);
+    return launch_step_m<S, SHAPE, MODE_EDGE>(insts, tiles, ntiles, half, s);
+}
+
+template <class S>
+static hipError_t launch_step_p(int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
                                 hipStream_t s) {
     switch (shape) {
-    case 0: return launch_step_t<S, A, FUSE, 0>(insts, tiles, ntiles, half, s);
-    case 1: return launch_step_t<S, A, FUSE, 1>(insts, tiles, ntiles, half, s);
-    case 2: return launch_step_t<S, A, FUSE, 2>(insts, tiles, ntiles, half, s);
-    case 3: return launch_step_t<S, A, FUSE, 3>(insts, tiles, ntiles, half, s);
-    case 4: return launch_step_t<S, A, FUSE, 4>(insts, tiles, ntiles, half, s);
-    case 5: return launch_step_t<S, A, FUSE, 5>(insts, tiles, ntiles, half, s);
-    case 6: return launch_step_t<S, A, FUSE, 6>(insts, tiles, ntiles, half, s);
+    case 0: return launch_step_t<S, 0>(kind, insts, tiles, ntiles, half, s);
+    case 1: return launch_step_t<S, 1>(kind, insts, tiles, ntiles, half, s);
+    case 2: return launch_step_t<S, 2>(kind, insts, tiles, ntiles, half, s);
+    case 3: return launch_step_t<S, 3>(kind, insts, tiles, ntiles, half, s);
+    case 4: return launch_step_t<S, 4>(kind, insts, tiles, ntiles, half, s);
+    case 5: return launch_step_t<S, 5>(kind, insts, tiles, ntiles, half, s);
+    case 6: return launch_step_t<S, 6>(kind, insts, tiles, ntiles, half, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_step(int prec, int shape, const Inst *insts, const Tile *tiles, int ntiles, int half,
+hipError_t launch_step(int prec, int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
                        hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    if (prec == PREC_F64) return launch_step_p<double, double, false>(shape, insts, tiles, ntiles, half, s);
-    return launch_step_p<float, float, true>(shape, insts, tiles, ntiles, half, s);
+    if (prec == PREC_F64) return launch_step_p<double>(shape, kind, insts, tiles, ntiles, half, s);
+    return launch_step_p<float>(shape, kind, insts, tiles, ntiles, half, s);
+}
+
+int tile_kind(int x0, int y0, int tx, int ty, int nx, int ny, int bc_y) {
+    const bool xin = x0 >= 2 && x0 + tx + 2 <= nx;
+    const bool yin = y0 >= 2 && y0 + ty + 2 <= ny;
+    if (xin && yin) return MODE_INTERIOR;
+    if (xin && ny == ty && y0 == 0 && bc_y == BC_PERIODIC) return MODE_TUBE;
+    return MODE_EDGE;
 }
 
 static dim3 grid16(int nx, int ny) { return dim3((nx + 15) / 16, (ny + 15) / 16); }
@@ -756,7 +1238,7 @@ hipError_t launch_diag(int prec, const Inst *insts, int inst, int nx, int ny, in
 }
 
 hipError_t launch_diag_final(const double *partials, int nparts, double *sums, hipStream_t s) {
-    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partials, nparts, sums);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kDiagBlock), 0, s, partials, nparts, sums);
     return hipGetLastError();
 }
 
