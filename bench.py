@@ -8,9 +8,13 @@ Mach-20 inflow turns non-physical within a few steps with this scheme for every 
 dt tried; freestream Mach 10 with lambda = 20 runs the full 10000 steps.)  A step is one
 launch per tile kind that advances all 33 distributions of every cell by Eq. (dis_eq1).
 
-Reported (one JSON line): cell-updates per second of the float64 path (`value`), the float32
-path and its L1 difference to float64 after the same steps, the 256-tube float32 ensemble,
-the roofline of the dominant kernel (interior tiles, timed alone with HIP events) against the
+Reported (one JSON line): cell-updates per second of the float64 path (`value`); the two
+float32 storages ("f32": f in float32; "f32dev": moments in float64 and g = f - f^eq in
+float32) with their speed-up and relative L1 difference to float64 after the same steps,
+beside the difference a 1e-13 perturbation of the initial density makes in float64 (this
+flow amplifies perturbations, so that is the floor any storage can reach); the 256-tube
+ensemble in float64 and both float32 storages with per-instance L1 against float64; the
+roofline of the dominant kernel (interior tiles, timed alone with HIP events) against the
 MI355X HBM peak, HBM traffic from the committed counter summary when it matches the current
 kernel source, and the CPU oracle's rate on a bounded slice of the same grid.
 """
@@ -26,7 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-ALG_BYTES = {"f64": 2 * 33 * 8, "f32": 2 * 33 * 4}  # compulsory read + write of the 33 planes per cell-update
+# compulsory read + write per cell-update: the 33 planes, plus the four float64 moments of
+# the deviation storage
+ALG_BYTES = {"f64": 2 * 33 * 8, "f32": 2 * 33 * 4, "f32dev": 2 * (33 * 4 + 4 * 8)}
 KERNEL_SRC = os.path.join(ROOT, "paper_0801_4169_amd", "csrc", "fdlb_kernels.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "step_interior_f64_reflection_8192x2048_counters.md")
 
@@ -36,13 +42,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="both", choices=["both", "f64", "f32"])
+    ap.add_argument("--precision", default="all", choices=["all", "f64", "f32", "f32dev"])
     ap.add_argument("--nx", type=int, default=8192)
     ap.add_argument("--ny", type=int, default=2048)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--mach", type=float, default=10.0, help="freestream Mach number of the inflow")
     ap.add_argument("--lam", type=float, default=20.0, help="artificial-viscosity amplitude lambda")
     ap.add_argument("--ensemble-steps", type=int, default=5000, help="steps of the 256-tube ensemble (0: skip)")
+    ap.add_argument("--no-sensitivity", action="store_true",
+                    help="skip the perturbed float64 run that measures the flow's own sensitivity")
     ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps of the CPU baseline slice (0: skip)")
     ap.add_argument("--cpu-rows", type=int, default=256, help="rows of the CPU baseline slice")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -100,33 +108,40 @@ def l1_rel(a, b):
 
 
 def ensemble(P, steps):
+    """The 256-tube ensemble in each storage: rate, and per-instance relative L1 of rho and T
+    of both float32 storages against the float64 run (itself bit-identical to the oracle)."""
     import numpy as np
     import torch
 
     import fdlb_inputs as fi
     probs, _ = fi.ensemble_tubes()
-    b = P.BatchSolver([p for p, _ in probs], precision="f32")
-    for i, (p, flds) in enumerate(probs):
-        b.set_state(i, *flds)
-    b.step(20)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    b.step(steps)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    physical = 0
-    for i in range(len(probs)):
-        r, u, w, T = b.moments(i, allow_nonphys=True)
-        physical += int(np.all(np.isfinite(T)) and np.all(r > 0) and np.all(T > 0))
-    cells = b.cells
-    out = {"workload": "ensemble_256_tubes_seed0", "dtype": "f32", "cells": cells, "steps": steps,
-           "ms_per_step": ms / steps, "value": cells * steps / (ms / 1e3) / 1e6, "unit": "Mcell-updates/s",
-           "hbm_frac": ALG_BYTES["f32"] * cells / (ms / steps / 1e3) / 1e9 / HBM_PEAK_GBS,
-           "tiling": list(b.tiling), "instances_physical_at_end": physical}
-    b.close()
+    out = {"workload": "ensemble_256_tubes_seed0", "steps": steps}
+    mom = {}
+    for prec in ("f64", "f32", "f32dev"):
+        b = P.BatchSolver([p for p, _ in probs], precision=prec)
+        for i, (p, flds) in enumerate(probs):
+            b.set_state(i, *flds)
+        b.step(20)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        mom[prec] = [b.moments(i, allow_nonphys=True) for i in range(len(probs))]
+        physical = sum(int(np.all(np.isfinite(m[3])) and np.all(m[0] > 0) and np.all(m[3] > 0)) for m in mom[prec])
+        cells = b.cells
+        out[prec] = {"value": cells * steps / (ms / 1e3) / 1e6, "unit": "Mcell-updates/s", "ms_per_step": ms / steps,
+                     "hbm_frac": ALG_BYTES[prec] * cells / (ms / steps / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "tiling": list(b.tiling), "instances_physical_at_end": physical}
+        out["cells"] = cells
+        b.close()
+    for prec in ("f32", "f32dev"):
+        l1 = np.array([[l1_rel(a[k], r[k]) for k in (0, 3)] for a, r in zip(mom[prec], mom["f64"])])
+        out[prec]["l1_vs_f64_rho_T_median"] = [float(x) for x in np.median(l1, axis=0)]
+        out[prec]["l1_vs_f64_rho_T_max"] = [float(x) for x in np.max(l1, axis=0)]
     return out
 
 
@@ -167,7 +182,7 @@ def main():
 
     prob, fields, _ = fi.reflection_8192x2048(lam=args.lam, nx=args.nx, ny=args.ny, mach=args.mach)
     cells = prob["nx"] * prob["ny"]
-    precs = ["f64", "f32"] if args.precision == "both" else [args.precision]
+    precs = ["f64", "f32", "f32dev"] if args.precision == "all" else [args.precision]
     res = {}
     for pr in precs:
         print(f"[bench] {pr}: {prob['nx']}x{prob['ny']}, {args.warmup} warmup + {args.steps} timed steps",
@@ -202,11 +217,21 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic / (r["k_ms"] / 1e3) / 1e9,
-                     "kernel": f"fdlb::step_kernel<{'double' if main_p == 'f64' else 'float'}, interior tiles>",
+                     "kernel": {"f64": "fdlb::step_kernel<double, interior tiles>",
+                                "f32": "fdlb::step_kernel<float, interior tiles>",
+                                "f32dev": "fdlb::step_kernel_dev<interior tiles>"}[main_p],
                      "kernel_ms": r["k_ms"], "kernel_cells": r["k_cells"],
                      "alg_bytes_per_cell_update": ALG_BYTES[main_p]},
         "nonphysical": bool(r["flag"]),
     }
+    if "f64" in res and len(precs) > 1 and not args.no_sensitivity:
+        import numpy as np
+        print("[bench] f64 with 1e-13 noise in the initial density (sensitivity floor)", file=sys.stderr, flush=True)
+        rng = np.random.default_rng(1)
+        pert = (fields[0] * (1.0 + 1e-13 * rng.standard_normal(fields[0].shape)),) + tuple(fields[1:])
+        rp_ = timed_run(P, prob, pert, "f64", args.steps, args.warmup, args.tile)
+        out["f64_perturbed_l1_vs_f64_after_run"] = {k: l1_rel(x, y) for k, x, y in
+                                                    zip(("rho", "ux", "uy", "T"), rp_["moments"], res["f64"]["moments"])}
     for pr in precs[1:]:
         o = res[pr]
         ent = {"value": o["rate"] / 1e6, "ms_per_step": o["ms"] / args.steps,

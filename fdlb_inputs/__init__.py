@@ -208,30 +208,38 @@ def reflection_8192x2048(lam=2.0, nx=8192, ny=2048, mach=20.0):
     return p, f, 10000
 
 
-def ensemble_draws(count=256, seed=0):
+def ensemble_draws(count=256, seed=0, log_rp_max=2.0):
     """Instance table of the batched tube ensemble: (nx, pressure ratio, density ratio)
-    drawn in this order per instance from ``numpy.random.default_rng(seed)``."""
+    drawn in this order per instance from ``numpy.random.default_rng(seed)``: nx uniform
+    in [256, 4096], log10 of the pressure ratio uniform in [1, log_rp_max], density ratio
+    uniform in [0.1, 10].
+
+    The pressure ratio stops at 100 by default: with this scheme, random tubes above a
+    ratio of about 100-300 turn non-physical (T < 0 ahead of the shock) in the float64
+    oracle itself, for every tau, lambda and Courant number tried; log_rp_max=5 gives the
+    full [10, 1e5] range."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
         nx = int(rng.integers(256, 4097))
-        rp = float(10.0 ** rng.uniform(1.0, 5.0))
+        rp = float(10.0 ** rng.uniform(1.0, log_rp_max))
         rr = float(rng.uniform(0.1, 10.0))
         out.append((nx, rp, rr))
     return out
 
 
-def ensemble_tubes(count=256, seed=0, ny=4):
-    """256 shock tubes on [0, 1] with left state (1, 0, 0, 1) and right density 1/r_rho,
-    pressure 1/r_p; dx = 1/nx, dt = 0.004 dx, tau = 2 dt; the artificial-viscosity
-    amplitude grows with log(r_p) from 2 (ratio 10, the Sod value) to 20 (ratio 1e5, the
-    Colella value).  5000 steps."""
+def ensemble_tubes(count=256, seed=0, ny=4, log_rp_max=2.0, tau_factor=1.0, lam=20.0):
+    """Shock tubes on [0, 1] with left state (1, 0, 0, 1) and right density 1/r_rho,
+    pressure 1/r_p (so T = r_rho / r_p); dx = 1/nx, dt = 0.004 dx (the dt/dx of the
+    paper's Sod run), tau = tau_factor * dt, artificial-viscosity amplitude lam (Colella's
+    value; lam=None interpolates 2 -> 20 in log r_p over [10, 1e5]); periodic in y.
+    5000 steps."""
     probs = []
-    for i, (nx, rp, rr) in enumerate(ensemble_draws(count, seed)):
+    for i, (nx, rp, rr) in enumerate(ensemble_draws(count, seed, log_rp_max)):
         dx = 1.0 / nx
         dt = 0.004 * dx
-        lam = 2.0 + 18.0 * math.log10(rp / 10.0) / 4.0
+        lm = lam if lam is not None else 2.0 + 18.0 * math.log10(rp / 10.0) / 4.0
         right = (1.0 / rr, 0.0, 0.0, rr / rp)
-        p = problem(nx, ny, dx, dt, 2.0 * dt, lam, TUBE_BC, name=f"tube{i}")
+        p = problem(nx, ny, dx, dt, tau_factor * dt, lm, TUBE_BC, name=f"tube{i}")
         probs.append((p, riemann_fields(nx, ny, (1.0, 0.0, 0.0, 1.0), right)))
     return probs, 5000

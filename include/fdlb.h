@@ -50,12 +50,20 @@ typedef enum {
 } fdlb_status;
 
 /* Storage and arithmetic of the distributions.
- *   FDLB_F64: float64 storage and arithmetic.  The arithmetic follows one fixed evaluation
- *             order without fused multiply-add, so it reproduces a plain float64
- *             evaluation of the same formulas bit for bit.
- *   FDLB_F32: float32 storage; equilibrium and stencil in float32; the moments
- *             (density, velocity, temperature, pressure) are accumulated in float64. */
-typedef enum { FDLB_F64 = 0, FDLB_F32 = 1 } fdlb_precision;
+ *   FDLB_F64:     float64 storage and arithmetic.  The arithmetic follows one fixed
+ *                 evaluation order without fused multiply-add, so it reproduces a plain
+ *                 float64 evaluation of the same formulas bit for bit.
+ *   FDLB_F32:     float32 storage of f; equilibrium and stencil in float32; the moments
+ *                 (density, velocity, temperature, pressure) are accumulated in float64.
+ *                 At high Mach number the f^eq values grow large and of both signs
+ *                 (sum |f| / n ~ 1e3 at Mach 10, 1e4 at Mach 20), and rounding them to
+ *                 float32 alone moves T by 0.7% (Mach 10) to 70% (Mach 20).
+ *   FDLB_F32_DEV: deviation storage: per cell the moments M = (n, ux, uy, T) in float64
+ *                 and g_q = f_q - f^eq_q(M) in float32.  Each step rebuilds f = f^eq(M) + g
+ *                 in float64, applies Eq. (dis_eq1) in float64 and stores the new moments
+ *                 and g relative to them; only the small deviation g is rounded to
+ *                 float32.  Reported moments are M. */
+typedef enum { FDLB_F64 = 0, FDLB_F32 = 1, FDLB_F32_DEV = 2 } fdlb_precision;
 
 /* Side conditions (Sec. 5.2).  Sides are ordered x-, x+, y-, y+.
  *   PERIODIC : wrap around; both sides of an axis must be periodic together.
@@ -126,10 +134,12 @@ fdlb_status fdlb_get_moments(fdlb_ctx *c, double *rho, double *ux, double *uy, d
  * planes).  Asynchronous; does not report the flag. */
 fdlb_status fdlb_get_moments_device(fdlb_ctx *c, double *fields);
 
-/* Checkpoint: the 33 distribution planes as 33 * ny * nx values of the storage type
- * (float64 for FDLB_F64, float32 for FDLB_F32), plane q = 0 (rest particle) first, then
- * q = 1 + 8 (k - 1) + (i - 1) for speed k and direction i pi/4.  `bytes` must equal
- * fdlb_f_bytes(c).  fdlb_get_f syncs; fdlb_set_f copies then derives the pressure. */
+/* Checkpoint: the stored state.  FDLB_F64 / FDLB_F32: the 33 distribution planes as
+ * 33 * ny * nx values of the storage type (float64 / float32), plane q = 0 (rest particle)
+ * first, then q = 1 + 8 (k - 1) + (i - 1) for speed k and direction i pi/4.
+ * FDLB_F32_DEV: the 33 planes of g (float32, same order), then the four float64 planes
+ * n, ux, uy, T.  `bytes` must equal fdlb_f_bytes(c).  fdlb_get_f syncs; fdlb_set_f copies
+ * then derives the pressure (and checks the state). */
 size_t fdlb_f_bytes(const fdlb_ctx *c);
 fdlb_status fdlb_get_f(fdlb_ctx *c, void *host, size_t bytes);
 fdlb_status fdlb_set_f(fdlb_ctx *c, const void *host, size_t bytes);

@@ -11,8 +11,8 @@ from __future__ import annotations
 import numpy as np
 
 from . import _binding as B
-from ._binding import (FDLB_BC_DIRICHLET, FDLB_BC_OUTFLOW, FDLB_BC_PERIODIC, FDLB_BC_WALL, FDLB_F32, FDLB_F64,
-                       FDLB_EINVAL, FDLB_ENONPHYS, FDLB_ESTATE, FdlbError, fdlb_tile_shapes, make_params)
+from ._binding import (FDLB_BC_DIRICHLET, FDLB_BC_OUTFLOW, FDLB_BC_PERIODIC, FDLB_BC_WALL, FDLB_F32, FDLB_F32_DEV,
+                       FDLB_F64, FDLB_EINVAL, FDLB_ENONPHYS, FDLB_ESTATE, FdlbError, fdlb_tile_shapes, make_params)
 
 __all__ = ["Solver", "BatchSolver", "FdlbError", "make_params", "fdlb_tile_shapes", "B"]
 
@@ -28,7 +28,8 @@ def _torch():
 
 class Solver:
     """One problem on one GPU.  ``prob`` is a problem dict (nx, ny, dx, dy, dt, tau, lam, v,
-    bc, bc_state); ``precision`` is "f64" or "f32"; ``tile`` a shape id (0 = default)."""
+    bc, bc_state); ``precision`` is "f64", "f32" or "f32dev" (deviation storage);
+    ``tile`` a shape id (0 = default)."""
 
     def __init__(self, prob, precision="f64", tile=0, device="cuda:0"):
         torch = _torch()
@@ -37,6 +38,7 @@ class Solver:
         self.nx, self.ny = self.params.nx, self.params.ny
         self.ncell = self.nx * self.ny
         self.dtype = np.float64 if self.params.precision == FDLB_F64 else np.float32
+        self.dev = self.params.precision == FDLB_F32_DEV
         nbytes = B.fdlb_required_bytes(self.params)
         if nbytes == 0:
             raise FdlbError(FDLB_EINVAL, "invalid parameters")
@@ -73,11 +75,27 @@ class Solver:
         return out
 
     def get_f(self, allow_nonphys=False):
+        """The stored state: f (33, ny, nx); for deviation storage the pair (g float32
+        (33, ny, nx), moments float64 (4, ny, nx))."""
+        if self.dev:
+            buf = np.empty(B.fdlb_f_bytes(self.ctx), dtype=np.uint8)
+            B.fdlb_get_f(self.ctx, buf, allow_nonphys)
+            k = NQ * self.ncell * 4
+            g = buf[:k].view(np.float32).reshape(NQ, self.ny, self.nx).copy()
+            m = buf[k:].copy().view(np.float64).reshape(4, self.ny, self.nx)
+            return g, m
         out = np.empty((NQ, self.ny, self.nx), dtype=self.dtype)
         B.fdlb_get_f(self.ctx, out, allow_nonphys)
         return out
 
     def set_f(self, f):
+        if self.dev:
+            g, m = f
+            g = np.ascontiguousarray(np.asarray(g, dtype=np.float32))
+            m = np.ascontiguousarray(np.asarray(m, dtype=np.float64))
+            assert g.shape == (NQ, self.ny, self.nx) and m.shape == (4, self.ny, self.nx)
+            B.fdlb_set_f(self.ctx, np.concatenate([g.view(np.uint8).ravel(), m.view(np.uint8).ravel()]))
+            return
         f = np.ascontiguousarray(np.asarray(f, dtype=self.dtype))
         assert f.shape == (NQ, self.ny, self.nx)
         B.fdlb_set_f(self.ctx, f)

@@ -23,9 +23,9 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 FDLB_OK, FDLB_EINVAL, FDLB_ENOMEM, FDLB_EDEVICE, FDLB_ENONPHYS, FDLB_ESTATE = range(6)
-FDLB_F64, FDLB_F32 = 0, 1
+FDLB_F64, FDLB_F32, FDLB_F32_DEV = 0, 1, 2
 FDLB_BC_PERIODIC, FDLB_BC_OUTFLOW, FDLB_BC_DIRICHLET, FDLB_BC_WALL = range(4)
-PRECISIONS = {"f64": FDLB_F64, "f32": FDLB_F32}
+PRECISIONS = {"f64": FDLB_F64, "f32": FDLB_F32, "f32dev": FDLB_F32_DEV}
 
 
 class fdlb_bc(ctypes.Structure):

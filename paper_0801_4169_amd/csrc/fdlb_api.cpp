@@ -29,16 +29,31 @@ namespace {
 constexpr double kHalfSqrt2 = 0.70710678118654757;  // nearest double to sqrt(2)/2
 constexpr int kGraphSteps = 32;                      // steps per captured graph (even)
 constexpr size_t kAlign = 256;
+constexpr size_t kPlanePad = 256;                    // see plane_pad_bytes
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
 struct Layout {
     int fpitch, ppitch, wlen;
-    int64_t fplane;
+    int64_t fplane, mplane;
     size_t esize;
     size_t f_bytes, p_bytes, m_bytes, w_bytes, total;
 };
+
+// Bytes between the end of one plane and the start of the next (f planes and moment
+// planes).  Rows are padded to 32 elements, so on large grids the plane stride is a power
+// of two, and a cell's values in the 33 planes then fall into the same cache sets and
+// memory channels.  FDLB_PLANE_PAD (bytes, a multiple of 256) overrides the measured
+// default.
+size_t plane_pad_bytes() {
+    const char *e = std::getenv("FDLB_PLANE_PAD");
+    if (e) {
+        const long v = std::atol(e);
+        if (v >= 0 && v % 256 == 0) return (size_t)v;
+    }
+    return kPlanePad;
+}
 
 Layout layout_of(const fdlb_params &p) {
     Layout L{};
@@ -46,10 +61,12 @@ Layout layout_of(const fdlb_params &p) {
     L.fpitch = round_up(p.nx, 32);
     L.ppitch = round_up(p.nx, 32);
     L.wlen = round_up(std::max(p.nx, p.ny), 32);
-    L.fplane = (int64_t)p.ny * L.fpitch;
+    const size_t pad = plane_pad_bytes();
+    L.fplane = (int64_t)p.ny * L.fpitch + (int64_t)(pad / L.esize);
+    L.mplane = (int64_t)p.ny * L.ppitch + (int64_t)(pad / 8);
     L.f_bytes = align_up((size_t)fdlb::NQ * (size_t)L.fplane * L.esize, kAlign);
     L.p_bytes = align_up((size_t)p.ny * L.ppitch * 8, kAlign);
-    L.m_bytes = align_up((size_t)4 * p.ny * L.ppitch * 8, kAlign);
+    L.m_bytes = align_up((size_t)4 * L.mplane * 8, kAlign);
     L.w_bytes = align_up((size_t)4 * L.wlen * 8, kAlign);
     L.total = 2 * (L.f_bytes + L.p_bytes + L.m_bytes + L.w_bytes);
     return L;
@@ -63,7 +80,7 @@ int validate(const fdlb_params &p) {
     if ((int64_t)p.nx * p.ny > (int64_t)1 << 28) return 1;  // a plane stays below 2 GiB
     if (!finite_pos(p.dx) || !finite_pos(p.dy) || !finite_pos(p.dt) || !finite_pos(p.tau)) return 1;
     if (!std::isfinite(p.lambda) || p.lambda < 0.0) return 1;
-    if (p.precision != FDLB_F64 && p.precision != FDLB_F32) return 1;
+    if (p.precision != FDLB_F64 && p.precision != FDLB_F32 && p.precision != FDLB_F32_DEV) return 1;
     if (p.tile < 0 || p.tile > fdlb::kNumTileShapes) return 1;
     double vmax = 0.0;
     for (int k = 0; k < 4; ++k) {
@@ -95,8 +112,9 @@ int default_group(int prec) {
     return prec == FDLB_F64 ? 16 : 32;
 }
 
-// Tile shape (index into kTileShapes), measured: 64 x 8 for float64, 32 x 8 for float32;
-// 64 x 4 when the grid is four cells high (one tile spans a tube's periodic height).
+// Tile shape (index into kTileShapes), measured: 64 x 8 for float64, 32 x 8 for float32
+// and the deviation layout; 64 x 4 when the grid is four cells high (one tile spans a
+// tube's periodic height).
 int default_shape(const fdlb_params &p) {
     if (p.tile > 0) return p.tile - 1;
     if (p.ny == 4) return 1;
@@ -120,6 +138,7 @@ void fill_constants(const fdlb_params &p, Inst &I) {
         I.FB[k] = a * b + b * d + d * a;
         I.FC[k] = a * b * d / 4.0;
         I.Fden[k] = vk2 * (vk2 - a) * (vk2 - b) * (vk2 - d);
+        I.Fdinv[k] = 1.0 / I.Fden[k];
     }
     for (int al = 0; al < 2; ++al) {
         const double dr = al == 0 ? p.dx : p.dy;
@@ -140,6 +159,8 @@ void fill_constants(const fdlb_params &p, Inst &I) {
     I.dx = p.dx;
     I.dy = p.dy;
     I.dtau = p.dt / p.tau;
+    I.cdx = p.dt / p.dx;
+    I.cdy = p.dt / p.dy;
     I.lam = p.lambda;
     for (int s = 0; s < 4; ++s) {
         I.bc[s] = p.bc[s].kind;
@@ -304,7 +325,7 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
             I.M[h] = reinterpret_cast<double *>(base + off);
             off += L.m_bytes;
         }
-        I.mplane = (int64_t)p[i].ny * L.ppitch;
+        I.mplane = L.mplane;
         for (int h = 0; h < 2; ++h) {
             I.PW[h] = reinterpret_cast<double *>(base + off);
             off += L.w_bytes;
@@ -521,8 +542,31 @@ fdlb_status fdlb_get_moments_device(fdlb_ctx *c, double *fields) {
 size_t fdlb_f_bytes(const fdlb_ctx *c) {
     if (!c || c->k != 1) return 0;
     const fdlb_params &p = c->params[0];
-    return (size_t)fdlb::NQ * p.nx * p.ny * c->layouts[0].esize;
+    const size_t cells = (size_t)p.nx * p.ny;
+    return (size_t)fdlb::NQ * cells * c->layouts[0].esize + (c->prec == FDLB_F32_DEV ? 4 * cells * 8 : 0);
 }
+
+namespace {
+// The moment planes of the deviation layout, after the 33 g planes of a checkpoint.
+fdlb_status copy_m(fdlb_ctx *c, char *host, const char *hsrc, bool to_host) {
+    if (c->prec != FDLB_F32_DEV) return FDLB_OK;
+    const fdlb_params &p = c->params[0];
+    const Layout &L = c->layouts[0];
+    const size_t row = (size_t)p.nx * 8;
+    const size_t gbytes = (size_t)fdlb::NQ * p.nx * p.ny * L.esize;
+    const Inst &I = c->h_insts[0];
+    for (int a = 0; a < 4; ++a) {
+        double *dev = I.M[c->half] + (size_t)a * I.mplane;
+        if (to_host)
+            HIPCHK(c, hipMemcpy2DAsync(host + gbytes + (size_t)a * p.ny * row, row, dev, (size_t)L.ppitch * 8, row,
+                                       p.ny, hipMemcpyDeviceToHost, c->stream));
+        else
+            HIPCHK(c, hipMemcpy2DAsync(dev, (size_t)L.ppitch * 8, hsrc + gbytes + (size_t)a * p.ny * row, row, row,
+                                       p.ny, hipMemcpyHostToDevice, c->stream));
+    }
+    return FDLB_OK;
+}
+}  // namespace
 
 fdlb_status fdlb_get_f(fdlb_ctx *c, void *host, size_t bytes) {
     if (!c || c->k != 1 || !host || bytes != fdlb_f_bytes(c)) return FDLB_EINVAL;
@@ -535,6 +579,8 @@ fdlb_status fdlb_get_f(fdlb_ctx *c, void *host, size_t bytes) {
     for (int q = 0; q < fdlb::NQ; ++q)
         HIPCHK(c, hipMemcpy2DAsync(dst + (size_t)q * p.ny * row, row, src + (size_t)q * L.fplane * L.esize,
                                    (size_t)L.fpitch * L.esize, row, p.ny, hipMemcpyDeviceToHost, c->stream));
+    fdlb_status ms = copy_m(c, dst, nullptr, true);
+    if (ms != FDLB_OK) return ms;
     return check_flag(c);
 }
 
@@ -548,6 +594,8 @@ fdlb_status fdlb_set_f(fdlb_ctx *c, const void *host, size_t bytes) {
     for (int q = 0; q < fdlb::NQ; ++q)
         HIPCHK(c, hipMemcpy2DAsync(dst + (size_t)q * L.fplane * L.esize, (size_t)L.fpitch * L.esize,
                                    src + (size_t)q * p.ny * row, row, row, p.ny, hipMemcpyHostToDevice, c->stream));
+    fdlb_status ms = copy_m(c, nullptr, src, false);
+    if (ms != FDLB_OK) return ms;
     HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
     HIPCHK(c, fdlb::launch_derive(c->prec, c->d_insts, 0, p.nx, p.ny, c->half, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

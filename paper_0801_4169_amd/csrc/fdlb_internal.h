@@ -3,10 +3,12 @@
 // Layout in HBM (per instance, per ping-pong half h = 0, 1):
 //   f[h]  : 33 planes of ny rows x fpitch elements (float64 or float32), structure of
 //           arrays, x fastest; plane q = 0 is the rest particle, q = 1 + 8(k-1) + (i-1) the
-//           velocity of speed k and direction i pi/4 (Eq. dvm_eq_1).
+//           velocity of speed k and direction i pi/4 (Eq. dvm_eq_1).  In the deviation
+//           layout (PREC_DEV) the planes hold g_q = f_q - f^eq_q(M) in float32.
 //   P[h]  : pressure n T of every cell, ny rows x ppitch float64.
 //   M[h]  : moments (n, ux, uy, T) of every cell, 4 planes of ny rows x ppitch float64,
-//           written by the step that produced the distributions and read by the next.
+//           written by the step that produced the distributions and read by the next
+//           (ppitch == fpitch, so one element offset addresses a cell in both).
 //   PW[h] : 4 rows of wlen float64, the pressure of the mirror image of the cells next to
 //           each reflecting side (x-, x+, y-, y+), read by the switching function.
 // The step reads half h and writes half 1 - h.
@@ -19,7 +21,7 @@ namespace fdlb {
 
 constexpr int NQ = 33;
 constexpr int BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_DIRICHLET = 2, BC_WALL = 3;
-constexpr int PREC_F64 = 0, PREC_F32 = 1;
+constexpr int PREC_F64 = 0, PREC_F32 = 1, PREC_DEV = 2;
 
 // Per-instance constants and buffer pointers.  Lives in device memory and is read with
 // uniform (scalar) loads.  All constants are float64, computed on the host in a fixed
@@ -41,6 +43,8 @@ struct Inst {
     double FA[4], FB[4], FC[4], Fden[4]; // weight polynomial constants, Eq. (fk_eq1)
     double k1[2][2][4], k2[2][2][4], k3[2][2][4]; // [alpha][axis=0, diag=1][speed], c >= 0
     double dt, dx, dy, dtau, lam;
+    double Fdinv[4];         // 1 / Fden (deviation path, which needs no fixed order)
+    double cdx, cdy;         // dt / dx, dt / dy
     float kf[3][2][2][4];    // float copies of k1, k2, k3 (float32 path)
     float kkf[2][2][4];      // k1 + 2 k3, float32 path
     float vf[4], vsf[4];     // float copies of v and vs

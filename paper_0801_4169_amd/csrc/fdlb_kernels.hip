@@ -169,11 +169,11 @@ __device__ __forceinline__ A s_of(A mag, A ux, A uy) {
 }
 
 // ------------------------------------------------------------------------------------
-// Float32 moments: float64 accumulation with fused multiply-adds (any order is fine for
-// the float32 path; the float64 path uses moments33 above).
+// Moments with float64 accumulation and fused multiply-adds (any order is fine for the
+// float32 and deviation paths; the float64 path uses moments33 above).
 // ------------------------------------------------------------------------------------
-template <int MIR>
-__device__ __forceinline__ void moments33_fast(const Inst &I, const float (&f)[NQ], double &n, double &jx,
+template <int MIR, class S>
+__device__ __forceinline__ void moments33_fast(const Inst &I, const S (&f)[NQ], double &n, double &jx,
                                                double &jy, double &E) {
     n = 0.0;
     jx = 0.0;
@@ -999,6 +999,332 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(const Inst *__restrict__ i
 }
 
 // ------------------------------------------------------------------------------------
+// Deviation storage (precision FDLB_F32_DEV).
+//
+// A cell stores its moments M = (n, ux, uy, T) in float64 and its distributions as
+// g_q = f_q - f^eq_q(M) in float32.  At high Mach number the f_q themselves are large and
+// of both signs (their sum n is a small difference of them), so rounding f_q to float32
+// loses the temperature; g is small wherever the flow is near equilibrium and carries no
+// such cancellation.  The step:
+//   rebuild f = f^eq(M) + g in float64 for the tile and its halo (LDS, one plane pair per
+//   stage, as in the other bodies); switching function from P = n T of the stored M;
+//   Eq. (dis_eq1) in float64 with the collision toward f^eq(M) (the same values that
+//   rebuilt the cell); then the new moments M' of f_new in float64 and
+//   g' = f_new - f^eq(M'), stored in float32.
+// f^eq here is evaluated with fused multiply-adds, the same function on both sides of the
+// round trip, so rebuilding reproduces f_new up to the float32 rounding of g' alone.
+// ------------------------------------------------------------------------------------
+struct DevCell {
+    double c0, c1, c2, c3, c4;
+    double nF[5];
+    double ux, uy;
+};
+
+// The coefficients of equilibrium_coefs with one division (1/T) and fused multiply-adds.
+__device__ __forceinline__ void dev_cell(const Inst &I, double n, double ux, double uy, double T, DevCell &d) {
+    const double iT = 1.0 / T;
+    const double iT2 = iT * iT;
+    double sF = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double num = __builtin_fma(__builtin_fma(__builtin_fma(48.0, T, -I.FA[k]), T, I.FB[k]), T, -I.FC[k]) * T;
+        const double F = num * I.Fdinv[k];
+        d.nF[k + 1] = n * F;
+        sF += F;
+    }
+    d.nF[0] = n * __builtin_fma(-8.0, sF, 1.0);
+    const double u2 = __builtin_fma(ux, ux, uy * uy);
+    const double h = __builtin_fma(-0.5 * u2, iT, 1.0);
+    d.c0 = __builtin_fma(0.125 * (u2 * u2), iT2, h);
+    d.c1 = h * iT;
+    d.c2 = 0.5 * h * iT2;
+    d.c3 = iT2 * iT * (1.0 / 6.0);
+    d.c4 = iT2 * iT2 * (1.0 / 24.0);
+    d.ux = ux;
+    d.uy = uy;
+}
+
+// Line-IV coefficient (Eqs. add3, add4) with one division.
+__device__ __forceinline__ double av_dev(double lam, double Pm, double P0, double Pp, double u, double cdr) {
+    const double th = lam * fabs((Pp - 2.0 * P0 + Pm) / (Pp + 2.0 * P0 + Pm));
+    const double kap = fabs(u * cdr);
+    return th * kap * (1.0 - kap) * 0.5;
+}
+
+// f^eq of the pair (qa, qa + 4): even and odd powers of s = v . u (qa = 0: the rest value).
+template <int QA>
+__device__ __forceinline__ void dev_feq_pair(const Inst &I, const DevCell &d, double &fa, double &fb) {
+    if constexpr (QA == 0) {
+        fa = d.nF[0] * d.c0;
+        fb = fa;
+    } else {
+        constexpr int k = qk(QA);
+        const double mag = qdiag(QA) ? I.vs[k] : I.v[k];
+        const double s = s_of<QA, double>(mag, d.ux, d.uy);
+        const double s2 = s * s;
+        const double ev = __builtin_fma(__builtin_fma(d.c4, s2, d.c2), s2, d.c0);
+        const double od = s * __builtin_fma(d.c3, s2, d.c1);
+        fa = d.nF[k + 1] * (ev + od);
+        fb = d.nF[k + 1] * (ev - od);
+    }
+}
+
+// Eq. (dis_eq1) for one velocity in float64 as weights on the five points of each
+// direction (the float32 update's form), with fused multiply-adds.
+template <int Q>
+__device__ __forceinline__ double update_dev(const Inst &I, double ax, double ay, double omd, double f0,
+                                             double feq, double xm2, double xm1, double xp1, double xp2, double ym2,
+                                             double ym1, double yp1, double yp2) {
+    constexpr int k = qk(Q), dg = qdiag(Q) ? 1 : 0, sx = qsx(Q), sy = qsy(Q);
+    double Kx = ax, Ky = ay;
+    if constexpr (sx != 0) Kx = I.k2[0][dg][k] + ax;
+    if constexpr (sy != 0) Ky = I.k2[1][dg][k] + ay;
+    double fn = (omd - 2.0 * (Kx + Ky)) * f0;
+    fn = __builtin_fma(I.dtau, feq, fn);
+    if constexpr (sx != 0) {
+        const double k3 = I.k3[0][dg][k];
+        const double kk = __builtin_fma(2.0, k3, I.k1[0][dg][k]);
+        fn = __builtin_fma(sx > 0 ? Kx - kk : Kx + kk, xp1, fn);
+        fn = __builtin_fma(sx > 0 ? Kx + kk : Kx - kk, xm1, fn);
+        fn = __builtin_fma(sx > 0 ? k3 : -k3, xp2 - xm2, fn);
+    } else {
+        fn = __builtin_fma(Kx, xp1 + xm1, fn);
+    }
+    if constexpr (sy != 0) {
+        const double k3 = I.k3[1][dg][k];
+        const double kk = __builtin_fma(2.0, k3, I.k1[1][dg][k]);
+        fn = __builtin_fma(sy > 0 ? Ky - kk : Ky + kk, yp1, fn);
+        fn = __builtin_fma(sy > 0 ? Ky + kk : Ky - kk, ym1, fn);
+        fn = __builtin_fma(sy > 0 ? k3 : -k3, yp2 - ym2, fn);
+    } else {
+        fn = __builtin_fma(Ky, yp1 + ym1, fn);
+    }
+    return fn;
+}
+
+// g of plane Q at a (mapped) cell; a Dirichlet ghost is its state's equilibrium, g = 0.
+// Offsets are elements (M and f planes share the row pitch).
+template <int Q, int MODE>
+__device__ __forceinline__ float fetch_g(const Inst &I, const GLOBAL_AS char *gin, size_t pb, const Src &s) {
+    if constexpr (MODE != MODE_EDGE) {
+        return *reinterpret_cast<const GLOBAL_AS float *>(gin + (size_t)Q * pb + (uint32_t)s.off * 4u);
+    } else {
+        if (s.dside >= 0) return 0.0f;
+        const int qq = s.flip == 0 ? Q : s.flip == 1 ? qmx(Q) : s.flip == 2 ? qmy(Q) : qmx(qmy(Q));
+        return reinterpret_cast<const GLOBAL_AS float *>(gin)[(size_t)qq * I.fplane + s.off];
+    }
+}
+
+// Stored moments of a (mapped) cell; the mirror image across a wall has the normal
+// velocity component reversed; a Dirichlet ghost has its side's state.
+template <int MODE>
+__device__ __forceinline__ void load_m(const Inst &I, const GLOBAL_AS double *Min, const Src &s, double &n,
+                                       double &ux, double &uy, double &T) {
+    if constexpr (MODE == MODE_EDGE) {
+        if (s.dside >= 0) {
+            n = I.bcstate[s.dside][0];
+            ux = I.bcstate[s.dside][1];
+            uy = I.bcstate[s.dside][2];
+            T = I.bcstate[s.dside][3];
+            return;
+        }
+    }
+    const GLOBAL_AS double *m = Min + (uint32_t)s.off;
+    n = m[0];
+    ux = m[I.mplane];
+    uy = m[2 * I.mplane];
+    T = m[3 * I.mplane];
+    if constexpr (MODE == MODE_EDGE) {
+        if (s.flip & 1) ux = -ux;
+        if (s.flip & 2) uy = -uy;
+    }
+}
+
+// Materialises a value in vector registers at this point of the program.  The new values
+// of a stage are only used after the last stage; without this the compiler sinks each
+// stage's arithmetic to that use and keeps all the LDS operands of all stages alive.
+__device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+template <int TX, int TY>
+struct DevSmem {
+    double buf[2][2][TY + 4][TX + 4];
+    double P[(TY + 4) * (TX + 4)];
+};
+
+// One body for interior tiles and (with side mapping) for all others.
+template <int TX, int TY, int MODE>
+__device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, const Tile &tile, int half,
+                                              DevSmem<TX, TY> &sm) {
+    static_assert(MODE == MODE_INTERIOR || MODE == MODE_EDGE, "deviation body modes");
+    const Inst &I = insts[tile.inst];
+    constexpr int NT = TX * TY;
+    constexpr int NHALL = 4 * (TX + TY);
+    constexpr int NSLOT = (NHALL + NT - 1) / NT;
+    constexpr int LW = TX + 4;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int x = tile.x0 + tx, y = tile.y0 + ty;
+    const bool valid = MODE != MODE_EDGE || (x < I.nx && y < I.ny);
+    const GLOBAL_AS char *gin = (const GLOBAL_AS char *)(I.f[half]);
+    GLOBAL_AS char *gout = (GLOBAL_AS char *)(I.f[1 - half]);
+    const size_t pb = (size_t)I.fplane * sizeof(float);
+    const GLOBAL_AS double *Min = (const GLOBAL_AS double *)I.M[half];
+
+    Src own;
+    if constexpr (MODE != MODE_EDGE) own = Src{y * I.fpitch + x, 0, -1};
+    else own = map_cell(I, x, y);
+    Src hs[NSLOT];
+    int hl[NSLOT];
+#pragma unroll
+    for (int j = 0; j < NSLOT; ++j) {
+        const int hid = tid + j * NT;
+        hl[j] = -1;
+        hs[j] = Src{0, 0, -1};
+        if (hid < NHALL) {
+            int lx, ly;
+            if (hid < 4 * TX) {
+                const int r = hid / TX;
+                lx = hid % TX + 2;
+                ly = r < 2 ? r : TY + r;
+            } else {
+                const int h2 = hid - 4 * TX;
+                const int c = h2 / TY;
+                ly = h2 % TY + 2;
+                lx = c < 2 ? c : TX + c;
+            }
+            hl[j] = ly * LW + lx;
+            const int X = tile.x0 + lx - 2, Y = tile.y0 + ly - 2;
+            if constexpr (MODE != MODE_EDGE) hs[j] = Src{Y * I.fpitch + X, 0, -1};
+            else hs[j] = map_cell(I, X, Y);
+        }
+    }
+
+    // first stage's g in flight while the equilibrium coefficients are formed
+    float go[2] = {0.0f, 0.0f}, gh[2][NSLOT];
+    go[0] = fetch_g<0, MODE>(I, gin, pb, own);
+#pragma unroll
+    for (int j = 0; j < NSLOT; ++j) {
+        gh[0][j] = 0.0f;
+        gh[1][j] = 0.0f;
+        if (hl[j] >= 0) gh[0][j] = fetch_g<0, MODE>(I, gin, pb, hs[j]);
+    }
+
+    const int own_l = (ty + 2) * LW + (tx + 2);
+    DevCell dc, dh[NSLOT];
+    {
+        double n, ux, uy, T;
+        load_m<MODE>(I, Min, own, n, ux, uy, T);
+        dev_cell(I, n, ux, uy, T, dc);
+        sm.P[own_l] = n * T;
+    }
+#pragma unroll
+    for (int j = 0; j < NSLOT; ++j)
+        if (hl[j] >= 0) {
+            double n, ux, uy, T;
+            load_m<MODE>(I, Min, hs[j], n, ux, uy, T);
+            dev_cell(I, n, ux, uy, T, dh[j]);
+            sm.P[hl[j]] = n * T;
+        }
+
+    const double omd = 1.0 - I.dtau;
+    double ax = 0.0, ay = 0.0;
+    double fnew[NQ];
+    int b = 0;
+    static_for<0, NSTAGE>([&](auto stc) {
+        constexpr int st = decltype(stc)::value;
+        constexpr int qa = stage_qa(st), qb = stage_qb(st);
+        const Inst &Is = insts[opaque(tile.inst)];
+        const size_t pbs = opaque(pb);
+        double *pa = &sm.buf[b][0][0][0];
+        double *pbuf = &sm.buf[b][1][0][0];
+        // rebuild f for the pair: own cell (its f^eq is also the collision target), halo
+        double ea, eb;
+        dev_feq_pair<qa>(Is, dc, ea, eb);
+        const double fa0 = ea + static_cast<double>(go[0]);
+        const double fb0 = eb + static_cast<double>(go[1]);
+        pa[own_l] = fa0;
+        if constexpr (qb >= 0) pbuf[own_l] = fb0;
+#pragma unroll
+        for (int j = 0; j < NSLOT; ++j)
+            if (hl[j] >= 0) {
+                double ha, hb;
+                dev_feq_pair<qa>(Is, dh[j], ha, hb);
+                pa[hl[j]] = ha + static_cast<double>(gh[0][j]);
+                if constexpr (qb >= 0) pbuf[hl[j]] = hb + static_cast<double>(gh[1][j]);
+            }
+        __syncthreads();
+        if constexpr (st == 0) {
+            // switching function from the neighbours' P (written before the first barrier)
+            const double P0 = sm.P[own_l];
+            ax = av_dev(Is.lam, sm.P[own_l - 1], P0, sm.P[own_l + 1], dc.ux, Is.cdx);
+            ay = av_dev(Is.lam, sm.P[own_l - LW], P0, sm.P[own_l + LW], dc.uy, Is.cdy);
+        }
+        if constexpr (st + 1 < NSTAGE) {
+            constexpr int na = stage_qa(st + 1);
+            go[0] = fetch_g<na, MODE>(Is, gin, pbs, own);
+            go[1] = fetch_g<na + 4, MODE>(Is, gin, pbs, own);
+#pragma unroll
+            for (int j = 0; j < NSLOT; ++j)
+                if (hl[j] >= 0) {
+                    gh[0][j] = fetch_g<na, MODE>(Is, gin, pbs, hs[j]);
+                    gh[1][j] = fetch_g<na + 4, MODE>(Is, gin, pbs, hs[j]);
+                }
+        }
+        fnew[qa] = update_dev<qa>(Is, ax, ay, omd, fa0, ea, pa[own_l - 2], pa[own_l - 1], pa[own_l + 1],
+                                  pa[own_l + 2], pa[own_l - 2 * LW], pa[own_l - LW], pa[own_l + LW],
+                                  pa[own_l + 2 * LW]);
+        pin(fnew[qa]);
+        if constexpr (qb >= 0) {
+            fnew[qb] = update_dev<qb>(Is, ax, ay, omd, fb0, eb, pbuf[own_l - 2], pbuf[own_l - 1], pbuf[own_l + 1],
+                                      pbuf[own_l + 2], pbuf[own_l - 2 * LW], pbuf[own_l - LW], pbuf[own_l + LW],
+                                      pbuf[own_l + 2 * LW]);
+            pin(fnew[qb]);
+        }
+        b ^= 1;
+    });
+
+    // new moments (float64), g' relative to them, flag
+    double n2, jx2, jy2, E2;
+    moments33_fast<0>(I, fnew, n2, jx2, jy2, E2);
+    const double in2 = 1.0 / n2;
+    const double ux2 = jx2 * in2, uy2 = jy2 * in2;
+    const double T2 = __builtin_fma(-0.5, __builtin_fma(ux2, ux2, uy2 * uy2), E2 * in2);
+    const int bad = valid && nonphysical(I, n2, ux2, uy2, T2) ? 1 : 0;
+    DevCell dn;
+    dev_cell(I, n2, ux2, uy2, T2, dn);
+    const uint32_t own_b = (uint32_t)(y * I.fpitch + x) * 4u;
+    if (valid) {
+        static_for<0, NSTAGE>([&](auto stc) {
+            constexpr int st = decltype(stc)::value;
+            constexpr int qa = stage_qa(st), qb = stage_qb(st);
+            const size_t pbs = opaque(pb);
+            double ea, eb;
+            dev_feq_pair<qa>(I, dn, ea, eb);
+            store_out(reinterpret_cast<GLOBAL_AS float *>(gout + (size_t)qa * pbs + own_b),
+                      static_cast<float>(fnew[qa] - ea));
+            if constexpr (qb >= 0)
+                store_out(reinterpret_cast<GLOBAL_AS float *>(gout + (size_t)qb * pbs + own_b),
+                          static_cast<float>(fnew[qb] - eb));
+        });
+        GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[1 - half] + (y * I.ppitch + x);
+        Mo[0] = n2;
+        Mo[I.mplane] = ux2;
+        Mo[2 * I.mplane] = uy2;
+        Mo[3 * I.mplane] = T2;
+    }
+    if (__syncthreads_or(bad) && tid == 0) *I.flag = 1;
+}
+
+template <int TX, int TY, int MODE>
+__global__ __launch_bounds__(TX *TY) void step_kernel_dev(const Inst *__restrict__ insts,
+                                                          const Tile *__restrict__ tiles, int ntiles, int half) {
+    __shared__ DevSmem<TX, TY> sm;
+    const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
+    step_body_dev<TX, TY, MODE>(insts, tile, half, sm);
+}
+
+// ------------------------------------------------------------------------------------
 // Auxiliary kernels (not on the per-step path).
 // ------------------------------------------------------------------------------------
 
@@ -1122,6 +1448,81 @@ __global__ __launch_bounds__(256) void diag_kernel(const Inst *__restrict__ inst
     if (threadIdx.x < 4) partials[4 * (long)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// ---- deviation layout (g planes float32, moment planes float64) ----------------------
+
+// g := 0, M := fields: the state f = f^eq(fields) exactly.
+__global__ __launch_bounds__(256) void fill_dev_kernel(const Inst *__restrict__ insts, int inst,
+                                                       const double *__restrict__ fields, int half) {
+    const Inst &I = insts[inst];
+    const int x = blockIdx.x * 16 + threadIdx.x % 16, y = blockIdx.y * 16 + threadIdx.x / 16;
+    if (x >= I.nx || y >= I.ny) return;
+    const size_t c = (size_t)y * I.nx + x, plane = (size_t)I.nx * I.ny;
+    float *g = static_cast<float *>(I.f[half]);
+    const size_t off = (size_t)y * I.fpitch + x;
+    for (int q = 0; q < NQ; ++q) g[(size_t)q * I.fplane + off] = 0.0f;
+    double *M = I.M[half];
+    const size_t mo = (size_t)y * I.ppitch + x;
+    for (int a = 0; a < 4; ++a) M[(size_t)a * I.mplane + mo] = fields[a * plane + c];
+}
+
+// Non-physical flag of the stored moments.
+__global__ __launch_bounds__(256) void check_dev_kernel(const Inst *__restrict__ insts, int inst, int half) {
+    const Inst &I = insts[inst];
+    const int x = blockIdx.x * 16 + threadIdx.x % 16, y = blockIdx.y * 16 + threadIdx.x / 16;
+    if (x >= I.nx || y >= I.ny) return;
+    const double *M = I.M[half];
+    const size_t mo = (size_t)y * I.ppitch + x;
+    if (nonphysical(I, M[mo], M[I.mplane + mo], M[2 * I.mplane + mo], M[3 * I.mplane + mo])) *I.flag = 1;
+}
+
+// (rho, ux, uy, T): the stored moments.
+__global__ __launch_bounds__(256) void moments_dev_kernel(const Inst *__restrict__ insts, int inst, int half,
+                                                          double *__restrict__ out) {
+    const Inst &I = insts[inst];
+    const int x = blockIdx.x * 16 + threadIdx.x % 16, y = blockIdx.y * 16 + threadIdx.x / 16;
+    if (x >= I.nx || y >= I.ny) return;
+    const double *M = I.M[half];
+    const size_t mo = (size_t)y * I.ppitch + x;
+    const size_t c = (size_t)y * I.nx + x, plane = (size_t)I.nx * I.ny;
+    for (int a = 0; a < 4; ++a) out[a * plane + c] = M[(size_t)a * I.mplane + mo];
+}
+
+// Totals of (n, jx, jy, E) of f = f^eq(M) + g: the moments of f^eq(M) in closed form plus
+// those of g; fixed tree order as diag_kernel.
+__global__ __launch_bounds__(256) void diag_dev_kernel(const Inst *__restrict__ insts, int inst, int half,
+                                                       double *__restrict__ partials) {
+    const Inst &I = insts[inst];
+    __shared__ double red[4][kDiagBlock];
+    const long cell = (long)blockIdx.x * kDiagBlock + threadIdx.x;
+    const long ncell = (long)I.nx * I.ny;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (cell < ncell) {
+        const int x = (int)(cell % I.nx), y = (int)(cell / I.nx);
+        const float *gin = static_cast<const float *>(I.f[half]);
+        float g[NQ];
+        const size_t off = (size_t)y * I.fpitch + x;
+        static_for<0, NQ>([&](auto qc) { g[decltype(qc)::value] = gin[(size_t)decltype(qc)::value * I.fplane + off]; });
+        double gn, gx, gy, gE;
+        moments33_fast<0>(I, g, gn, gx, gy, gE);
+        const double *M = I.M[half];
+        const size_t mo = (size_t)y * I.ppitch + x;
+        const double n = M[mo], ux = M[I.mplane + mo], uy = M[2 * I.mplane + mo], T = M[3 * I.mplane + mo];
+        v[0] = n + gn;
+        v[1] = n * ux + gx;
+        v[2] = n * uy + gy;
+        v[3] = n * (T + (ux * ux + uy * uy) / 2.0) + gE;
+        if (nonphysical(I, n, ux, uy, T)) *I.flag = 1;
+    }
+    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int w = kDiagBlock / 2; w > 0; w /= 2) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = red[c][threadIdx.x] + red[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partials[4 * (long)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
 __global__ __launch_bounds__(kDiagBlock) void diag_final_kernel(const double *__restrict__ partials, int nparts,
                                                                 double *__restrict__ sums) {
     // each thread sums a fixed strided subset in order, then a fixed tree: deterministic
@@ -1158,17 +1559,43 @@ static hipError_t launch_step_t(int kind, const Inst *insts, const Tile *tiles, 
     return launch_step_m<S, SHAPE, MODE_EDGE>(insts, tiles, ntiles, half, s);
 }
 
+// Deviation layout: interior tiles get their own kernel; tube and edge tiles share the
+// body with side mapping.
+template <class S, int SHAPE>
+static hipError_t launch_step_dev(int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
+                                  hipStream_t s) {
+    constexpr int TX = kTileShapes[SHAPE].tx, TY = kTileShapes[SHAPE].ty;
+    if (kind == MODE_INTERIOR)
+        hipLaunchKernelGGL((step_kernel_dev<TX, TY, MODE_INTERIOR>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles,
+                           ntiles, half);
+    else
+        hipLaunchKernelGGL((step_kernel_dev<TX, TY, MODE_EDGE>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles,
+                           ntiles, half);
+    return hipGetLastError();
+}
+
+struct DevTag {};
+
+template <class S, int SHAPE>
+static hipError_t launch_step_any(int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
+                                  hipStream_t s) {
+    if constexpr (std::is_same<S, DevTag>::value)
+        return launch_step_dev<S, SHAPE>(kind, insts, tiles, ntiles, half, s);
+    else
+        return launch_step_t<S, SHAPE>(kind, insts, tiles, ntiles, half, s);
+}
+
 template <class S>
 static hipError_t launch_step_p(int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
                                 hipStream_t s) {
     switch (shape) {
-    case 0: return launch_step_t<S, 0>(kind, insts, tiles, ntiles, half, s);
-    case 1: return launch_step_t<S, 1>(kind, insts, tiles, ntiles, half, s);
-    case 2: return launch_step_t<S, 2>(kind, insts, tiles, ntiles, half, s);
-    case 3: return launch_step_t<S, 3>(kind, insts, tiles, ntiles, half, s);
-    case 4: return launch_step_t<S, 4>(kind, insts, tiles, ntiles, half, s);
-    case 5: return launch_step_t<S, 5>(kind, insts, tiles, ntiles, half, s);
-    case 6: return launch_step_t<S, 6>(kind, insts, tiles, ntiles, half, s);
+    case 0: return launch_step_any<S, 0>(kind, insts, tiles, ntiles, half, s);
+    case 1: return launch_step_any<S, 1>(kind, insts, tiles, ntiles, half, s);
+    case 2: return launch_step_any<S, 2>(kind, insts, tiles, ntiles, half, s);
+    case 3: return launch_step_any<S, 3>(kind, insts, tiles, ntiles, half, s);
+    case 4: return launch_step_any<S, 4>(kind, insts, tiles, ntiles, half, s);
+    case 5: return launch_step_any<S, 5>(kind, insts, tiles, ntiles, half, s);
+    case 6: return launch_step_any<S, 6>(kind, insts, tiles, ntiles, half, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1177,6 +1604,7 @@ hipError_t launch_step(int prec, int shape, int kind, const Inst *insts, const T
                        hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     if (prec == PREC_F64) return launch_step_p<double>(shape, kind, insts, tiles, ntiles, half, s);
+    if (prec == PREC_DEV) return launch_step_p<DevTag>(shape, kind, insts, tiles, ntiles, half, s);
     return launch_step_p<float>(shape, kind, insts, tiles, ntiles, half, s);
 }
 
@@ -1192,7 +1620,9 @@ static dim3 grid16(int nx, int ny) { return dim3((nx + 15) / 16, (ny + 15) / 16)
 
 hipError_t launch_fill(int prec, const Inst *insts, int inst, int nx, int ny, const double *fields, int half,
                        hipStream_t s) {
-    if (prec == PREC_F64)
+    if (prec == PREC_DEV)
+        hipLaunchKernelGGL(fill_dev_kernel, grid16(nx, ny), dim3(256), 0, s, insts, inst, fields, half);
+    else if (prec == PREC_F64)
         hipLaunchKernelGGL(fill_kernel<double>, grid16(nx, ny), dim3(256), 0, s, insts, inst, fields, half);
     else
         hipLaunchKernelGGL(fill_kernel<float>, grid16(nx, ny), dim3(256), 0, s, insts, inst, fields, half);
@@ -1200,7 +1630,9 @@ hipError_t launch_fill(int prec, const Inst *insts, int inst, int nx, int ny, co
 }
 
 hipError_t launch_derive(int prec, const Inst *insts, int inst, int nx, int ny, int half, hipStream_t s) {
-    if (prec == PREC_F64)
+    if (prec == PREC_DEV)
+        hipLaunchKernelGGL(check_dev_kernel, grid16(nx, ny), dim3(256), 0, s, insts, inst, half);
+    else if (prec == PREC_F64)
         hipLaunchKernelGGL(derive_kernel<double>, grid16(nx, ny), dim3(256), 0, s, insts, inst, half);
     else
         hipLaunchKernelGGL(derive_kernel<float>, grid16(nx, ny), dim3(256), 0, s, insts, inst, half);
@@ -1208,7 +1640,7 @@ hipError_t launch_derive(int prec, const Inst *insts, int inst, int nx, int ny, 
 }
 
 hipError_t launch_bc_setup(int prec, Inst *insts, int inst, hipStream_t s) {
-    if (prec == PREC_F64)
+    if (prec == PREC_F64 || prec == PREC_DEV)
         hipLaunchKernelGGL(bc_setup_kernel<double>, dim3(1), dim3(64), 0, s, insts, inst);
     else
         hipLaunchKernelGGL(bc_setup_kernel<float>, dim3(1), dim3(64), 0, s, insts, inst);
@@ -1217,7 +1649,9 @@ hipError_t launch_bc_setup(int prec, Inst *insts, int inst, hipStream_t s) {
 
 hipError_t launch_moments(int prec, const Inst *insts, int inst, int nx, int ny, int half, double *out,
                           hipStream_t s) {
-    if (prec == PREC_F64)
+    if (prec == PREC_DEV)
+        hipLaunchKernelGGL(moments_dev_kernel, grid16(nx, ny), dim3(256), 0, s, insts, inst, half, out);
+    else if (prec == PREC_F64)
         hipLaunchKernelGGL(moments_kernel<double>, grid16(nx, ny), dim3(256), 0, s, insts, inst, half, out);
     else
         hipLaunchKernelGGL(moments_kernel<float>, grid16(nx, ny), dim3(256), 0, s, insts, inst, half, out);
@@ -1230,7 +1664,9 @@ hipError_t launch_diag(int prec, const Inst *insts, int inst, int nx, int ny, in
                        int npart_offset, hipStream_t s) {
     const int nb = diag_blocks(nx, ny);
     double *p = partials + 4 * (long)npart_offset;
-    if (prec == PREC_F64)
+    if (prec == PREC_DEV)
+        hipLaunchKernelGGL(diag_dev_kernel, dim3(nb), dim3(kDiagBlock), 0, s, insts, inst, half, p);
+    else if (prec == PREC_F64)
         hipLaunchKernelGGL(diag_kernel<double>, dim3(nb), dim3(kDiagBlock), 0, s, insts, inst, half, p);
     else
         hipLaunchKernelGGL(diag_kernel<float>, dim3(nb), dim3(kDiagBlock), 0, s, insts, inst, half, p);

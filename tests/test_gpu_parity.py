@@ -300,9 +300,7 @@ def test_colella_literal_tau_bitwise_while_finite(P):
 
 def test_ensemble_all_256_tubes_bitwise(P):
     """The batched ensemble (256 tubes of 256..4096 cells, one launch per step), every
-    instance against its own oracle run.  Cold right states (T down to 1e-6) pass through
-    transient T < 0 cells, in the oracle as on the GPU; the values stay finite and agree bit
-    for bit."""
+    instance against its own oracle run."""
     say("ensemble 256 tubes, 20 steps")
     probs, _ = fi.ensemble_tubes()
     b = P.BatchSolver([p for p, _ in probs], precision="f64")
@@ -310,9 +308,9 @@ def test_ensemble_all_256_tubes_bitwise(P):
         b.set_state(i, *flds)
     b.step(20)
     for i, (p, flds) in enumerate(probs):
-        mb = b.moments(i, allow_nonphys=True)
-        f_ref, _ = oracle.run_f(p, oracle.init_state(p, flds), 20, nthreads=NTHR)
-        assert np.all(np.isfinite(f_ref)), i
+        mb = b.moments(i)
+        f_ref, bad = oracle.run_f(p, oracle.init_state(p, flds), 20, nthreads=NTHR)
+        assert bad == -1, i
         for x, y in zip(mb, oracle.fields(p, f_ref)):
             assert np.array_equal(x, y), i
     b.close()
@@ -320,8 +318,8 @@ def test_ensemble_all_256_tubes_bitwise(P):
 
 def test_ensemble_f32_l1_bounds(P):
     """Float32 ensemble after 500 steps against float64 oracle runs of a few instances
-    (smallest, largest, highest pressure ratio): L1 of rho, T below 1e-5, of u below 1e-4
-    (relative to the largest |u|)."""
+    (smallest and largest grid, highest pressure ratio): L1 of rho, T below 1e-5, of u
+    below 1e-4 (relative to the largest |u|)."""
     say("ensemble f32, 500 steps")
     probs, _ = fi.ensemble_tubes()
     b = P.BatchSolver([p for p, _ in probs], precision="f32")
@@ -329,13 +327,11 @@ def test_ensemble_f32_l1_bounds(P):
         b.set_state(i, *flds)
     b.step(500)
     draws = fi.ensemble_draws()
-    # instances that stay physical in float64 (pressure ratio below 30): smallest and
-    # largest grid among them
-    ok = [i for i in range(256) if draws[i][1] < 30.0]
-    pick = {min(ok, key=lambda i: draws[i][0]), max(ok, key=lambda i: draws[i][0])}
+    pick = {min(range(256), key=lambda i: draws[i][0]), max(range(256), key=lambda i: draws[i][0]),
+            max(range(256), key=lambda i: draws[i][1])}
     for i in sorted(pick):
         p, flds = probs[i]
-        m32 = b.moments(i, allow_nonphys=True)
+        m32 = b.moments(i)
         m64, bad = oracle.run_state(p, flds, 500, nthreads=NTHR)
         assert bad == -1
         l1 = [np.mean(np.abs(a - c)) for a, c in zip(m32, m64)]
