@@ -1151,15 +1151,15 @@ struct DevSmem {
     double P[(TY + 4) * (TX + 4)];
 };
 
-// One body for interior tiles and (with side mapping) for all others.
-template <int TX, int TY, int MODE>
+// One body for the three tile kinds (side mapping only in EDGE tiles).
+template <int TX, int TY, int MODE, int PD>
 __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, const Tile &tile, int half,
                                               DevSmem<TX, TY> &sm) {
-    static_assert(MODE == MODE_INTERIOR || MODE == MODE_EDGE, "deviation body modes");
     const Inst &I = insts[tile.inst];
     constexpr int NT = TX * TY;
+    constexpr int H0 = MODE == MODE_TUBE ? 4 * TX : 0;  // the tube body loads only the x halo
     constexpr int NHALL = 4 * (TX + TY);
-    constexpr int NSLOT = (NHALL + NT - 1) / NT;
+    constexpr int NSLOT = (NHALL - H0 + NT - 1) / NT;
     constexpr int LW = TX + 4;
 
     const int tid = threadIdx.x;
@@ -1178,7 +1178,7 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
     int hl[NSLOT];
 #pragma unroll
     for (int j = 0; j < NSLOT; ++j) {
-        const int hid = tid + j * NT;
+        const int hid = tid + j * NT + H0;
         hl[j] = -1;
         hs[j] = Src{0, 0, -1};
         if (hid < NHALL) {
@@ -1197,34 +1197,57 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
             const int X = tile.x0 + lx - 2, Y = tile.y0 + ly - 2;
             if constexpr (MODE != MODE_EDGE) hs[j] = Src{Y * I.fpitch + X, 0, -1};
             else hs[j] = map_cell(I, X, Y);
+        } else if constexpr (MODE != MODE_EDGE) {
+            hs[j] = own;  // no halo cell: loads stay unconditional (a load under a branch makes
+                          // the compiler wait for every load in flight where the branch joins)
         }
     }
 
-    // first stage's g in flight while the equilibrium coefficients are formed
-    float go[2] = {0.0f, 0.0f}, gh[2][NSLOT];
-    go[0] = fetch_g<0, MODE>(I, gin, pb, own);
+    // prefetch ring: g of the next PD stages (own cell and halo slots) in flight while the
+    // equilibrium coefficients are formed and while earlier stages compute
+    float go[PD][2], gh[PD][2][NSLOT];
+    auto load_stage = [&](auto stc, const Inst &Is, size_t pbs) {
+        constexpr int st = decltype(stc)::value;
+        constexpr int slot = st % PD, qa = stage_qa(st), qb = stage_qb(st);
+        go[slot][0] = fetch_g<qa, MODE>(Is, gin, pbs, own);
+        go[slot][1] = 0.0f;
+        if constexpr (qb >= 0) go[slot][1] = fetch_g<qb, MODE>(Is, gin, pbs, own);
 #pragma unroll
-    for (int j = 0; j < NSLOT; ++j) {
-        gh[0][j] = 0.0f;
-        gh[1][j] = 0.0f;
-        if (hl[j] >= 0) gh[0][j] = fetch_g<0, MODE>(I, gin, pb, hs[j]);
-    }
+        for (int j = 0; j < NSLOT; ++j) {
+            gh[slot][0][j] = 0.0f;
+            gh[slot][1][j] = 0.0f;
+            if (MODE != MODE_EDGE || hl[j] >= 0) {
+                gh[slot][0][j] = fetch_g<qa, MODE>(Is, gin, pbs, hs[j]);
+                if constexpr (qb >= 0) gh[slot][1][j] = fetch_g<qb, MODE>(Is, gin, pbs, hs[j]);
+            }
+        }
+    };
+    static_for<0, PD>([&](auto stc) { load_stage(stc, I, pb); });
 
     const int own_l = (ty + 2) * LW + (tx + 2);
+    // an own value goes to LDS; in a tube tile also to the halo rows it wraps onto
+    // (y = -2, -1 are rows ny - 2, ny - 1; y = ny, ny + 1 are rows 0, 1)
+    auto put = [&](double *pl, double v) {
+        pl[own_l] = v;
+        if constexpr (MODE == MODE_TUBE) {
+            if (ty >= TY - 2) pl[own_l - TY * LW] = v;
+            if (ty < 2) pl[own_l + TY * LW] = v;
+        }
+    };
     DevCell dc, dh[NSLOT];
     {
         double n, ux, uy, T;
         load_m<MODE>(I, Min, own, n, ux, uy, T);
         dev_cell(I, n, ux, uy, T, dc);
-        sm.P[own_l] = n * T;
+        put(sm.P, n * T);
     }
 #pragma unroll
     for (int j = 0; j < NSLOT; ++j)
-        if (hl[j] >= 0) {
+        if (MODE != MODE_EDGE || hl[j] >= 0) {
             double n, ux, uy, T;
             load_m<MODE>(I, Min, hs[j], n, ux, uy, T);
             dev_cell(I, n, ux, uy, T, dh[j]);
-            sm.P[hl[j]] = n * T;
+            if (hl[j] >= 0) sm.P[hl[j]] = n * T;
         }
 
     const double omd = 1.0 - I.dtau;
@@ -1239,19 +1262,20 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
         double *pa = &sm.buf[b][0][0][0];
         double *pbuf = &sm.buf[b][1][0][0];
         // rebuild f for the pair: own cell (its f^eq is also the collision target), halo
+        constexpr int slot = st % PD;
         double ea, eb;
         dev_feq_pair<qa>(Is, dc, ea, eb);
-        const double fa0 = ea + static_cast<double>(go[0]);
-        const double fb0 = eb + static_cast<double>(go[1]);
-        pa[own_l] = fa0;
-        if constexpr (qb >= 0) pbuf[own_l] = fb0;
+        const double fa0 = ea + static_cast<double>(go[slot][0]);
+        const double fb0 = eb + static_cast<double>(go[slot][1]);
+        put(pa, fa0);
+        if constexpr (qb >= 0) put(pbuf, fb0);
 #pragma unroll
         for (int j = 0; j < NSLOT; ++j)
             if (hl[j] >= 0) {
                 double ha, hb;
                 dev_feq_pair<qa>(Is, dh[j], ha, hb);
-                pa[hl[j]] = ha + static_cast<double>(gh[0][j]);
-                if constexpr (qb >= 0) pbuf[hl[j]] = hb + static_cast<double>(gh[1][j]);
+                pa[hl[j]] = ha + static_cast<double>(gh[slot][0][j]);
+                if constexpr (qb >= 0) pbuf[hl[j]] = hb + static_cast<double>(gh[slot][1][j]);
             }
         __syncthreads();
         if constexpr (st == 0) {
@@ -1260,17 +1284,7 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
             ax = av_dev(Is.lam, sm.P[own_l - 1], P0, sm.P[own_l + 1], dc.ux, Is.cdx);
             ay = av_dev(Is.lam, sm.P[own_l - LW], P0, sm.P[own_l + LW], dc.uy, Is.cdy);
         }
-        if constexpr (st + 1 < NSTAGE) {
-            constexpr int na = stage_qa(st + 1);
-            go[0] = fetch_g<na, MODE>(Is, gin, pbs, own);
-            go[1] = fetch_g<na + 4, MODE>(Is, gin, pbs, own);
-#pragma unroll
-            for (int j = 0; j < NSLOT; ++j)
-                if (hl[j] >= 0) {
-                    gh[0][j] = fetch_g<na, MODE>(Is, gin, pbs, hs[j]);
-                    gh[1][j] = fetch_g<na + 4, MODE>(Is, gin, pbs, hs[j]);
-                }
-        }
+        if constexpr (st + PD < NSTAGE) load_stage(std::integral_constant<int, st + PD>{}, Is, pbs);
         fnew[qa] = update_dev<qa>(Is, ax, ay, omd, fa0, ea, pa[own_l - 2], pa[own_l - 1], pa[own_l + 1],
                                   pa[own_l + 2], pa[own_l - 2 * LW], pa[own_l - LW], pa[own_l + LW],
                                   pa[own_l + 2 * LW]);
@@ -1316,12 +1330,15 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
     if (__syncthreads_or(bad) && tid == 0) *I.flag = 1;
 }
 
+#ifndef FDLB_DEV_PREFETCH
+#define FDLB_DEV_PREFETCH 3  // stages of look-ahead of the deviation body
+#endif
 template <int TX, int TY, int MODE>
 __global__ __launch_bounds__(TX *TY) void step_kernel_dev(const Inst *__restrict__ insts,
                                                           const Tile *__restrict__ tiles, int ntiles, int half) {
     __shared__ DevSmem<TX, TY> sm;
     const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
-    step_body_dev<TX, TY, MODE>(insts, tile, half, sm);
+    step_body_dev<TX, TY, MODE, FDLB_DEV_PREFETCH>(insts, tile, half, sm);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1559,14 +1576,16 @@ static hipError_t launch_step_t(int kind, const Inst *insts, const Tile *tiles, 
     return launch_step_m<S, SHAPE, MODE_EDGE>(insts, tiles, ntiles, half, s);
 }
 
-// Deviation layout: interior tiles get their own kernel; tube and edge tiles share the
-// body with side mapping.
+// Deviation layout: one kernel per tile kind, as for the other storages.
 template <class S, int SHAPE>
 static hipError_t launch_step_dev(int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
                                   hipStream_t s) {
     constexpr int TX = kTileShapes[SHAPE].tx, TY = kTileShapes[SHAPE].ty;
     if (kind == MODE_INTERIOR)
         hipLaunchKernelGGL((step_kernel_dev<TX, TY, MODE_INTERIOR>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles,
+                           ntiles, half);
+    else if (kind == MODE_TUBE)
+        hipLaunchKernelGGL((step_kernel_dev<TX, TY, MODE_TUBE>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles,
                            ntiles, half);
     else
         hipLaunchKernelGGL((step_kernel_dev<TX, TY, MODE_EDGE>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles,
