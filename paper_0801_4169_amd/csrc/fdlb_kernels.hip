@@ -1145,16 +1145,16 @@ __device__ __forceinline__ void load_m(const Inst &I, const GLOBAL_AS double *Mi
 // stage's arithmetic to that use and keeps all the LDS operands of all stages alive.
 __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 
-template <int TX, int TY>
+template <int TX, int TY, int UPS>
 struct DevSmem {
-    double buf[2][2][TY + 4][TX + 4];
+    double buf[2][2 * UPS][TY + 4][TX + 4];
     double P[(TY + 4) * (TX + 4)];
 };
 
 // One body for the three tile kinds (side mapping only in EDGE tiles).
-template <int TX, int TY, int MODE, int PD>
+template <int TX, int TY, int MODE, int PD, int UPS>
 __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, const Tile &tile, int half,
-                                              DevSmem<TX, TY> &sm) {
+                                              DevSmem<TX, TY, UPS> &sm) {
     const Inst &I = insts[tile.inst];
     constexpr int NT = TX * TY;
     constexpr int H0 = MODE == MODE_TUBE ? 4 * TX : 0;  // the tube body loads only the x halo
@@ -1203,26 +1203,36 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
         }
     }
 
+    // Units: unit 0 is the rest plane, unit u >= 1 the plane pair of stage u of the other
+    // bodies (stage_qa / stage_qb); a stage here processes UPS units between two barriers.
+    constexpr int NSTG = (NSTAGE + UPS - 1) / UPS;
+
     // prefetch ring: g of the next PD stages (own cell and halo slots) in flight while the
     // equilibrium coefficients are formed and while earlier stages compute
-    float go[PD][2], gh[PD][2][NSLOT];
+    float go[PD][UPS][2], gh[PD][UPS][2][NSLOT];
     auto load_stage = [&](auto stc, const Inst &Is, size_t pbs) {
         constexpr int st = decltype(stc)::value;
-        constexpr int slot = st % PD, qa = stage_qa(st), qb = stage_qb(st);
-        go[slot][0] = fetch_g<qa, MODE>(Is, gin, pbs, own);
-        go[slot][1] = 0.0f;
-        if constexpr (qb >= 0) go[slot][1] = fetch_g<qb, MODE>(Is, gin, pbs, own);
+        constexpr int slot = st % PD;
+        static_for<0, UPS>([&](auto ic) {
+            constexpr int i = decltype(ic)::value, u = st * UPS + i;
+            if constexpr (u < NSTAGE) {
+                constexpr int qa = stage_qa(u), qb = stage_qb(u);
+                go[slot][i][0] = fetch_g<qa, MODE>(Is, gin, pbs, own);
+                go[slot][i][1] = 0.0f;
+                if constexpr (qb >= 0) go[slot][i][1] = fetch_g<qb, MODE>(Is, gin, pbs, own);
 #pragma unroll
-        for (int j = 0; j < NSLOT; ++j) {
-            gh[slot][0][j] = 0.0f;
-            gh[slot][1][j] = 0.0f;
-            if (MODE != MODE_EDGE || hl[j] >= 0) {
-                gh[slot][0][j] = fetch_g<qa, MODE>(Is, gin, pbs, hs[j]);
-                if constexpr (qb >= 0) gh[slot][1][j] = fetch_g<qb, MODE>(Is, gin, pbs, hs[j]);
+                for (int j = 0; j < NSLOT; ++j) {
+                    gh[slot][i][0][j] = 0.0f;
+                    gh[slot][i][1][j] = 0.0f;
+                    if (MODE != MODE_EDGE || hl[j] >= 0) {
+                        gh[slot][i][0][j] = fetch_g<qa, MODE>(Is, gin, pbs, hs[j]);
+                        if constexpr (qb >= 0) gh[slot][i][1][j] = fetch_g<qb, MODE>(Is, gin, pbs, hs[j]);
+                    }
+                }
             }
-        }
+        });
     };
-    static_for<0, PD>([&](auto stc) { load_stage(stc, I, pb); });
+    static_for<0, (PD < NSTG ? PD : NSTG)>([&](auto stc) { load_stage(stc, I, pb); });
 
     const int own_l = (ty + 2) * LW + (tx + 2);
     // an own value goes to LDS; in a tube tile also to the halo rows it wraps onto
@@ -1252,31 +1262,39 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
 
     const double omd = 1.0 - I.dtau;
     double ax = 0.0, ay = 0.0;
+    // the new values are needed again after the last stage: g' is taken against their own
+    // moments
     double fnew[NQ];
     int b = 0;
-    static_for<0, NSTAGE>([&](auto stc) {
+    static_for<0, NSTG>([&](auto stc) {
         constexpr int st = decltype(stc)::value;
-        constexpr int qa = stage_qa(st), qb = stage_qb(st);
+        constexpr int slot = st % PD;
         const Inst &Is = insts[opaque(tile.inst)];
         const size_t pbs = opaque(pb);
-        double *pa = &sm.buf[b][0][0][0];
-        double *pbuf = &sm.buf[b][1][0][0];
-        // rebuild f for the pair: own cell (its f^eq is also the collision target), halo
-        constexpr int slot = st % PD;
-        double ea, eb;
-        dev_feq_pair<qa>(Is, dc, ea, eb);
-        const double fa0 = ea + static_cast<double>(go[slot][0]);
-        const double fb0 = eb + static_cast<double>(go[slot][1]);
-        put(pa, fa0);
-        if constexpr (qb >= 0) put(pbuf, fb0);
+        // rebuild f for the stage's planes: own cell (its f^eq is also the collision
+        // target) and halo
+        double e[UPS][2], f0[UPS][2];
+        static_for<0, UPS>([&](auto ic) {
+            constexpr int i = decltype(ic)::value, u = st * UPS + i;
+            if constexpr (u < NSTAGE) {
+                constexpr int qa = stage_qa(u), qb = stage_qb(u);
+                double *pa = &sm.buf[b][2 * i][0][0];
+                double *pbuf = &sm.buf[b][2 * i + 1][0][0];
+                dev_feq_pair<qa>(Is, dc, e[i][0], e[i][1]);
+                f0[i][0] = e[i][0] + static_cast<double>(go[slot][i][0]);
+                f0[i][1] = e[i][1] + static_cast<double>(go[slot][i][1]);
+                put(pa, f0[i][0]);
+                if constexpr (qb >= 0) put(pbuf, f0[i][1]);
 #pragma unroll
-        for (int j = 0; j < NSLOT; ++j)
-            if (hl[j] >= 0) {
-                double ha, hb;
-                dev_feq_pair<qa>(Is, dh[j], ha, hb);
-                pa[hl[j]] = ha + static_cast<double>(gh[slot][0][j]);
-                if constexpr (qb >= 0) pbuf[hl[j]] = hb + static_cast<double>(gh[slot][1][j]);
+                for (int j = 0; j < NSLOT; ++j)
+                    if (hl[j] >= 0) {
+                        double ha, hb;
+                        dev_feq_pair<qa>(Is, dh[j], ha, hb);
+                        pa[hl[j]] = ha + static_cast<double>(gh[slot][i][0][j]);
+                        if constexpr (qb >= 0) pbuf[hl[j]] = hb + static_cast<double>(gh[slot][i][1][j]);
+                    }
             }
+        });
         __syncthreads();
         if constexpr (st == 0) {
             // switching function from the neighbours' P (written before the first barrier)
@@ -1284,17 +1302,25 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
             ax = av_dev(Is.lam, sm.P[own_l - 1], P0, sm.P[own_l + 1], dc.ux, Is.cdx);
             ay = av_dev(Is.lam, sm.P[own_l - LW], P0, sm.P[own_l + LW], dc.uy, Is.cdy);
         }
-        if constexpr (st + PD < NSTAGE) load_stage(std::integral_constant<int, st + PD>{}, Is, pbs);
-        fnew[qa] = update_dev<qa>(Is, ax, ay, omd, fa0, ea, pa[own_l - 2], pa[own_l - 1], pa[own_l + 1],
-                                  pa[own_l + 2], pa[own_l - 2 * LW], pa[own_l - LW], pa[own_l + LW],
-                                  pa[own_l + 2 * LW]);
-        pin(fnew[qa]);
-        if constexpr (qb >= 0) {
-            fnew[qb] = update_dev<qb>(Is, ax, ay, omd, fb0, eb, pbuf[own_l - 2], pbuf[own_l - 1], pbuf[own_l + 1],
-                                      pbuf[own_l + 2], pbuf[own_l - 2 * LW], pbuf[own_l - LW], pbuf[own_l + LW],
-                                      pbuf[own_l + 2 * LW]);
-            pin(fnew[qb]);
-        }
+        if constexpr (st + PD < NSTG) load_stage(std::integral_constant<int, st + PD>{}, Is, pbs);
+        static_for<0, UPS>([&](auto ic) {
+            constexpr int i = decltype(ic)::value, u = st * UPS + i;
+            if constexpr (u < NSTAGE) {
+                constexpr int qa = stage_qa(u), qb = stage_qb(u);
+                const double *pa = &sm.buf[b][2 * i][0][0];
+                const double *pbuf = &sm.buf[b][2 * i + 1][0][0];
+                fnew[qa] = update_dev<qa>(Is, ax, ay, omd, f0[i][0], e[i][0], pa[own_l - 2], pa[own_l - 1],
+                                          pa[own_l + 1], pa[own_l + 2], pa[own_l - 2 * LW], pa[own_l - LW],
+                                          pa[own_l + LW], pa[own_l + 2 * LW]);
+                pin(fnew[qa]);
+                if constexpr (qb >= 0) {
+                    fnew[qb] = update_dev<qb>(Is, ax, ay, omd, f0[i][1], e[i][1], pbuf[own_l - 2], pbuf[own_l - 1],
+                                              pbuf[own_l + 1], pbuf[own_l + 2], pbuf[own_l - 2 * LW],
+                                              pbuf[own_l - LW], pbuf[own_l + LW], pbuf[own_l + 2 * LW]);
+                    pin(fnew[qb]);
+                }
+            }
+        });
         b ^= 1;
     });
 
@@ -1315,11 +1341,11 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
             const size_t pbs = opaque(pb);
             double ea, eb;
             dev_feq_pair<qa>(I, dn, ea, eb);
-            store_out(reinterpret_cast<GLOBAL_AS float *>(gout + (size_t)qa * pbs + own_b),
-                      static_cast<float>(fnew[qa] - ea));
+            const float ga = static_cast<float>(fnew[qa] - ea);
+            const float gb = qb >= 0 ? static_cast<float>(fnew[qb] - eb) : 0.0f;
+            store_out(reinterpret_cast<GLOBAL_AS float *>(gout + (size_t)qa * pbs + own_b), ga);
             if constexpr (qb >= 0)
-                store_out(reinterpret_cast<GLOBAL_AS float *>(gout + (size_t)qb * pbs + own_b),
-                          static_cast<float>(fnew[qb] - eb));
+                store_out(reinterpret_cast<GLOBAL_AS float *>(gout + (size_t)qb * pbs + own_b), gb);
         });
         GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[1 - half] + (y * I.ppitch + x);
         Mo[0] = n2;
@@ -1333,12 +1359,15 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
 #ifndef FDLB_DEV_PREFETCH
 #define FDLB_DEV_PREFETCH 3  // stages of look-ahead of the deviation body
 #endif
+#ifndef FDLB_DEV_UPS
+#define FDLB_DEV_UPS 1       // plane units (rest plane or plane pair) per stage
+#endif
 template <int TX, int TY, int MODE>
 __global__ __launch_bounds__(TX *TY) void step_kernel_dev(const Inst *__restrict__ insts,
                                                           const Tile *__restrict__ tiles, int ntiles, int half) {
-    __shared__ DevSmem<TX, TY> sm;
+    __shared__ DevSmem<TX, TY, FDLB_DEV_UPS> sm;
     const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
-    step_body_dev<TX, TY, MODE, FDLB_DEV_PREFETCH>(insts, tile, half, sm);
+    step_body_dev<TX, TY, MODE, FDLB_DEV_PREFETCH, FDLB_DEV_UPS>(insts, tile, half, sm);
 }
 
 // ------------------------------------------------------------------------------------
