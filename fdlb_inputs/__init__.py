@@ -167,6 +167,27 @@ def sod_tube(nx=400, ny=4, dx=2.5e-3, dt=1e-5, tau=2e-5, lam=2.0):
     return p, riemann_fields(nx, ny, SOD_L, SOD_R), 1000
 
 
+# Tubes of Sec. 5.1 with the paper's parameters (the domain, not printed, is read as [0, 1])
+LAX_L, LAX_R = (0.445, 0.698, 0.0, 7.928), (0.5, 0.0, 0.0, 1.142)
+SJO_L, SJO_R = (1.0, -2.0, 0.0, 0.4), (1.0, 2.0, 0.0, 0.4)
+TWO_L, TWO_R = (5.99924, 19.5975, 0.0, 76.8254), (5.99242, -6.19633, 0.0, 7.69222)
+
+
+def paper_tube(name, ny=4):
+    """(problem, fields, steps) of a tube of Sec. 5.1 at the paper's dx, dt, tau, lambda and
+    end time: "sod" (Sec. 5.1.1, t = 0.2), "lax" (5.1.2, t = 0.2), "sjogreen" (5.1.3,
+    t = 0.018), "two_shocks" (5.1.5, t = 0.12)."""
+    spec = {"sod": (1e-3, 1e-5, 1e-4, 2.0, 20000, SOD_L, SOD_R),
+            "lax": (1e-3, 1e-5, 1e-4, 1.0, 20000, LAX_L, LAX_R),
+            "sjogreen": (3e-3, 1e-5, 1e-5, 1.8, 1800, SJO_L, SJO_R),
+            "two_shocks": (2e-3, 1e-5, 1e-5, 1.0, 12000, TWO_L, TWO_R)}[name]
+    dx, dt, tau, lam, steps, L, R = spec
+    nx = int(round(1.0 / dx))
+    nx += nx % 2
+    p = problem(nx, ny, dx, dt, tau, lam, TUBE_BC, name=f"{name}_{nx}x{ny}")
+    return p, riemann_fields(nx, ny, L, R), steps
+
+
 def colella_tube(nx=4000, ny=4, dx=2.5e-4, dt=1e-6, tau=2e-6, lam=20.0):
     """Colella's explosion problem (Sec. 5.1.4 states, pressure ratio 1e5) on 4000 x 4,
     20000 steps to t = 0.02."""

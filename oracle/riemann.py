@@ -61,11 +61,41 @@ def star_state(left, right, gamma=2.0, tol=1e-14, maxit=200):
     return p, 0.5 * (ul + ur) + 0.5 * (fr - fl)
 
 
+def _sample_vacuum(rl, ul, pl, al, rr, ur, pr, ar, xi, gamma):
+    """Data that generate vacuum: a left and a right rarefaction whose tails bound a vacuum
+    (rho = p = 0) between uL + 2 aL / (gamma - 1) and uR - 2 aR / (gamma - 1)."""
+    g1 = (gamma - 1.0) / (gamma + 1.0)
+    tl = ul + 2.0 * al / (gamma - 1.0)
+    tr = ur - 2.0 * ar / (gamma - 1.0)
+    rho = np.empty_like(xi)
+    u = np.empty_like(xi)
+    p = np.empty_like(xi)
+    for idx, s in np.ndenumerate(xi):
+        if s <= ul - al:
+            st = (rl, ul, pl)
+        elif s < tl:
+            c = 2.0 / (gamma + 1.0) + g1 / al * (ul - s)
+            st = (rl * c ** (2.0 / (gamma - 1.0)), 2.0 / (gamma + 1.0) * (al + 0.5 * (gamma - 1.0) * ul + s),
+                  pl * c ** (2.0 * gamma / (gamma - 1.0)))
+        elif s <= tr:
+            st = (0.0, s, 0.0)
+        elif s < ur + ar:
+            c = 2.0 / (gamma + 1.0) - g1 / ar * (ur - s)
+            st = (rr * c ** (2.0 / (gamma - 1.0)), 2.0 / (gamma + 1.0) * (-ar + 0.5 * (gamma - 1.0) * ur + s),
+                  pr * c ** (2.0 * gamma / (gamma - 1.0)))
+        else:
+            st = (rr, ur, pr)
+        rho[idx], u[idx], p[idx] = st
+    return rho, u, p
+
+
 def sample(left, right, xi, gamma=2.0):
     """Primitive state (rho, u, p) at similarity coordinates xi = (x - x0) / t."""
     rl, ul, pl = map(float, left)
     rr, ur, pr = map(float, right)
     al, ar = math.sqrt(gamma * pl / rl), math.sqrt(gamma * pr / rr)
+    if 2.0 * (al + ar) / (gamma - 1.0) <= ur - ul:
+        return _sample_vacuum(rl, ul, pl, al, rr, ur, pr, ar, np.asarray(xi, dtype=np.float64), gamma)
     ps, us = star_state(left, right, gamma)
     g1 = (gamma - 1.0) / (gamma + 1.0)
     xi = np.asarray(xi, dtype=np.float64)
@@ -123,4 +153,5 @@ def tube_solution(left_rhouT, right_rhouT, x, x0, t, gamma=2.0):
         rho, u, _, T = map(float, s)
         return (rho, u, rho * T)
     rho, u, p = sample(prim(left_rhouT), prim(right_rhouT), (np.asarray(x) - x0) / t, gamma)
-    return rho, u, p / rho
+    T = np.divide(p, rho, out=np.zeros_like(p), where=rho > 0)  # T = 0 in a vacuum
+    return rho, u, T
