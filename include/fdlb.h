@@ -70,7 +70,13 @@ typedef enum { FDLB_F64 = 0, FDLB_F32 = 1, FDLB_F32_DEV = 2 } fdlb_precision;
  *   OUTFLOW  : zero gradient, the ghost cells copy the edge cell ("supersonic outflow").
  *   DIRICHLET: the ghost cells hold f^eq of the side's (rho, ux, uy, T).
  *   WALL     : reflecting wall, the specular mirror of the cells inside about the cell
- *              face (the velocity component normal to the wall reversed). */
+ *              face (the velocity component normal to the wall reversed).
+ * A non-periodic side may have a lower segment with a condition of its own (the double
+ * Mach reflection of Sec. 5.2.2: a wall that begins at x = 0.08; a top state that changes
+ * at a point moving with the shock).  Ghost cells whose centre coordinate along the side
+ * (x on the y sides, y on the x sides; cell i has centre (i + 1/2) dx) is below
+ * split + split_rate * t take lo_kind and the lo state, where t = steps * dt and steps
+ * counts the steps since the state was set (fdlb_set_clock changes it). */
 typedef enum {
     FDLB_BC_PERIODIC = 0,
     FDLB_BC_OUTFLOW = 1,
@@ -82,6 +88,10 @@ typedef struct {
     int32_t kind;   /* fdlb_bc_kind */
     int32_t pad_;
     double rho, ux, uy, T; /* used by FDLB_BC_DIRICHLET only */
+    int32_t lo_kind;       /* condition of the lower segment; FDLB_BC_PERIODIC (0): none */
+    int32_t pad2_;
+    double lo_rho, lo_ux, lo_uy, lo_T; /* the lower segment's Dirichlet state */
+    double split, split_rate;          /* end of the lower segment: split + split_rate * t */
 } fdlb_bc;
 
 typedef struct {
@@ -150,6 +160,11 @@ fdlb_status fdlb_diag(fdlb_ctx *c, double sums[4], int32_t *nonphys);
 
 /* Steps taken since the last state was set. */
 int64_t fdlb_steps_done(const fdlb_ctx *c);
+
+/* Sets the step count that times the moving side segments (t = steps * dt) and
+ * fdlb_steps_done, for example to resume a checkpoint taken after `steps` steps.  Setting
+ * a state resets it to 0.  Enqueued. */
+fdlb_status fdlb_set_clock(fdlb_ctx *c, int64_t steps);
 
 void fdlb_destroy(fdlb_ctx *c);
 const char *fdlb_strerror(fdlb_status s);

@@ -53,6 +53,11 @@ class Params(ctypes.Structure):
         ("lines", ctypes.c_int32),
         ("theta_fixed", ctypes.c_int32),
         ("theta_value", ctypes.c_double),
+        ("bc_lo", ctypes.c_int32 * 4),
+        ("bc_lo_state", (ctypes.c_double * 4) * 4),
+        ("split", ctypes.c_double * 4),
+        ("split_rate", ctypes.c_double * 4),
+        ("step0", ctypes.c_int64),
     ]
 
 
@@ -91,8 +96,9 @@ def _vec(v):
     return np.ascontiguousarray(np.asarray(v, dtype=np.float64))
 
 
-def params(prob, lines=15, theta_fixed=False, theta_value=0.0):
-    """ctypes parameter block from a problem dict (see ``fdlb_inputs.problem``)."""
+def params(prob, lines=15, theta_fixed=False, theta_value=0.0, step0=0):
+    """ctypes parameter block from a problem dict (see ``fdlb_inputs.problem``); ``step0``
+    is the step number of the first step (time-dependent side segments)."""
     p = Params()
     p.nx, p.ny = prob["nx"], prob["ny"]
     p.dx, p.dy, p.dt, p.tau, p.lam = prob["dx"], prob["dy"], prob["dt"], prob["tau"], prob["lam"]
@@ -104,6 +110,15 @@ def params(prob, lines=15, theta_fixed=False, theta_value=0.0):
     p.lines = lines
     p.theta_fixed = 1 if theta_fixed else 0
     p.theta_value = theta_value
+    for k, seg in enumerate(prob.get("lower", (None,) * 4)):
+        if seg is None:
+            continue
+        kind, state, split, rate = seg
+        p.bc_lo[k] = kind
+        for c in range(4):
+            p.bc_lo_state[k][c] = state[c]
+        p.split[k], p.split_rate[k] = split, rate
+    p.step0 = step0
     return p
 
 

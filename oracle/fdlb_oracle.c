@@ -68,6 +68,15 @@ typedef struct {
     int32_t lines;           /* bit 0..3 = lines I..IV of Eq. (dis_eq1); 15 = full scheme */
     int32_t theta_fixed;     /* 0: switching function Eq. (add4); 1: theta := theta_value */
     double theta_value;
+    /* Lower segment of a side (the double Mach reflection of Sec. 5.2.2: a wall that begins
+     * at x = 0.08, a top state that changes at a moving point).  Ghost cells whose centre
+     * coordinate along the side (x on the y sides, y on the x sides) lies below
+     * split[s] + split_rate[s] * t, t = (step0 + step) * dt, take bc_lo[s] and its state;
+     * bc_lo[s] = 0 (periodic) means the side has no lower segment. */
+    int32_t bc_lo[4];
+    double bc_lo_state[4][4];
+    double split[4], split_rate[4];
+    int64_t step0;
 } orc_params;
 
 /* Direction table of Eq. (dvm_eq_1) for i = 1..8: cos(i pi/4), sin(i pi/4) with the exact
@@ -256,7 +265,7 @@ typedef struct {
     REAL *g;                   /* f with ghost frame, [NQ][gy][gx] */
     REAL *P;                   /* pressure on the interior plus a one-cell ring, [ny+2][nx+2] */
     REAL *mom;                 /* (n, ux, uy, T) per interior cell, [4][ny][nx] */
-    REAL bcf[4][NQ];           /* Dirichlet ghost vectors per side */
+    REAL bcf[8][NQ];           /* Dirichlet ghost vectors per side, then per lower segment */
     REAL k1[2][NQ], k2[2][NQ], k3[2][NQ]; /* line coefficients per direction alpha */
     REAL dtau, dtdx, dtdy;
 } grid_t;
@@ -289,10 +298,14 @@ static int grid_init(grid_t *G, const orc_params *p)
         }
     }
     G->dtau = (REAL)p->dt / (REAL)p->tau;
-    for (int side = 0; side < 4; ++side)
+    for (int side = 0; side < 4; ++side) {
         if (p->bc[side] == ORC_DIRICHLET)
             feq(&G->m, (REAL)p->bc_state[side][0], (REAL)p->bc_state[side][1],
                 (REAL)p->bc_state[side][2], (REAL)p->bc_state[side][3], G->bcf[side]);
+        if (p->bc_lo[side] == ORC_DIRICHLET)
+            feq(&G->m, (REAL)p->bc_lo_state[side][0], (REAL)p->bc_lo_state[side][1],
+                (REAL)p->bc_lo_state[side][2], (REAL)p->bc_lo_state[side][3], G->bcf[4 + side]);
+    }
     return 0;
 }
 
@@ -305,40 +318,58 @@ static void grid_free(grid_t *G)
 
 static int wrap(int a, int n) { return ((a % n) + n) % n; }
 
+/* Condition of the ghost cells of `side` at position i along it (row y on the x sides,
+ * column x on the y sides) at time t: the side's own, or its lower segment's.  Returns the
+ * kind and sets *slot to the index of the Dirichlet vector. */
+static int side_kind(const orc_params *p, int side, int i, double t, int *slot)
+{
+    *slot = side;
+    if (p->bc_lo[side] != ORC_PERIODIC) {
+        const double d = side < 2 ? p->dy : p->dx;
+        const double c = ((double)i + 0.5) * d;
+        const double s = p->split[side] + p->split_rate[side] * t;
+        if (c < s) {
+            *slot = 4 + side;
+            return p->bc_lo[side];
+        }
+    }
+    return p->bc[side];
+}
+
 /* Ghost layers (two per side, corners unused) from the interior, per boundary kind. */
-static void fill_ghosts(grid_t *G)
+static void fill_ghosts(grid_t *G, double t)
 {
     const int nx = G->nx, ny = G->ny;
     for (int q = 0; q < NQ; ++q) {
         for (int y = 0; y < ny; ++y)
             for (int gl = 1; gl <= 2; ++gl) {
-                int xl = -gl, xr = nx - 1 + gl;
-                switch (G->p.bc[0]) {
+                int xl = -gl, xr = nx - 1 + gl, sl;
+                switch (side_kind(&G->p, 0, y, t, &sl)) {
                 case ORC_PERIODIC: GI(G, q, xl, y) = GI(G, q, wrap(xl, nx), y); break;
                 case ORC_OUTFLOW: GI(G, q, xl, y) = GI(G, q, 0, y); break;
-                case ORC_DIRICHLET: GI(G, q, xl, y) = G->bcf[0][q]; break;
+                case ORC_DIRICHLET: GI(G, q, xl, y) = G->bcf[sl][q]; break;
                 default: GI(G, q, xl, y) = GI(G, mirror_x(q), -1 - xl, y); break;
                 }
-                switch (G->p.bc[1]) {
+                switch (side_kind(&G->p, 1, y, t, &sl)) {
                 case ORC_PERIODIC: GI(G, q, xr, y) = GI(G, q, wrap(xr, nx), y); break;
                 case ORC_OUTFLOW: GI(G, q, xr, y) = GI(G, q, nx - 1, y); break;
-                case ORC_DIRICHLET: GI(G, q, xr, y) = G->bcf[1][q]; break;
+                case ORC_DIRICHLET: GI(G, q, xr, y) = G->bcf[sl][q]; break;
                 default: GI(G, q, xr, y) = GI(G, mirror_x(q), 2 * nx - 1 - xr, y); break;
                 }
             }
         for (int x = 0; x < nx; ++x)
             for (int gl = 1; gl <= 2; ++gl) {
-                int yb = -gl, yt = ny - 1 + gl;
-                switch (G->p.bc[2]) {
+                int yb = -gl, yt = ny - 1 + gl, sl;
+                switch (side_kind(&G->p, 2, x, t, &sl)) {
                 case ORC_PERIODIC: GI(G, q, x, yb) = GI(G, q, x, wrap(yb, ny)); break;
                 case ORC_OUTFLOW: GI(G, q, x, yb) = GI(G, q, x, 0); break;
-                case ORC_DIRICHLET: GI(G, q, x, yb) = G->bcf[2][q]; break;
+                case ORC_DIRICHLET: GI(G, q, x, yb) = G->bcf[sl][q]; break;
                 default: GI(G, q, x, yb) = GI(G, mirror_y(q), x, -1 - yb); break;
                 }
-                switch (G->p.bc[3]) {
+                switch (side_kind(&G->p, 3, x, t, &sl)) {
                 case ORC_PERIODIC: GI(G, q, x, yt) = GI(G, q, x, wrap(yt, ny)); break;
                 case ORC_OUTFLOW: GI(G, q, x, yt) = GI(G, q, x, ny - 1); break;
-                case ORC_DIRICHLET: GI(G, q, x, yt) = G->bcf[3][q]; break;
+                case ORC_DIRICHLET: GI(G, q, x, yt) = G->bcf[sl][q]; break;
                 default: GI(G, q, x, yt) = GI(G, mirror_y(q), x, 2 * ny - 1 - yt); break;
                 }
             }
@@ -477,13 +508,13 @@ static long run(const orc_params *p, REAL *f, long nsteps, int nthreads, int *er
     long first_bad = -1;
     for (long s = 0; s < nsteps; ++s) {
         load_interior(&G, f);
-        fill_ghosts(&G);
+        fill_ghosts(&G, (double)(p->step0 + s) * p->dt);
         all_moments(&G, nthreads);
         if (first_bad < 0 && nonphysical(&G)) first_bad = s;
         update(&G, f, nthreads);
     }
     load_interior(&G, f);
-    fill_ghosts(&G);
+    fill_ghosts(&G, (double)(p->step0 + nsteps) * p->dt);
     all_moments(&G, nthreads);
     if (first_bad < 0 && nonphysical(&G)) first_bad = nsteps + 1;
     grid_free(&G);
@@ -501,6 +532,9 @@ static int check_params(const orc_params *p)
     for (int s = 0; s < 4; ++s) {
         if (p->bc[s] < 0 || p->bc[s] > 3) return 1;
         if (p->bc[s] == ORC_WALL && ((s < 2 && p->nx < 2) || (s >= 2 && p->ny < 2))) return 1;
+        if (p->bc_lo[s] < 0 || p->bc_lo[s] > 3) return 1;
+        if (p->bc_lo[s] != ORC_PERIODIC && p->bc[s] == ORC_PERIODIC) return 1;
+        if (p->bc_lo[s] == ORC_WALL && ((s < 2 && p->nx < 2) || (s >= 2 && p->ny < 2))) return 1;
     }
     if ((p->bc[0] == ORC_PERIODIC) != (p->bc[1] == ORC_PERIODIC)) return 1;
     if ((p->bc[2] == ORC_PERIODIC) != (p->bc[3] == ORC_PERIODIC)) return 1;

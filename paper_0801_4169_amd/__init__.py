@@ -122,6 +122,10 @@ class Solver:
     def steps_done(self):
         return B.fdlb_steps_done(self.ctx)
 
+    def set_clock(self, steps):
+        """Step count that times moving side segments (e.g. after restoring a checkpoint)."""
+        B.fdlb_set_clock(self.ctx, steps)
+
     def close(self):
         if getattr(self, "ctx", None):
             B.fdlb_destroy(self.ctx)

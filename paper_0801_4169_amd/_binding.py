@@ -30,7 +30,10 @@ PRECISIONS = {"f64": FDLB_F64, "f32": FDLB_F32, "f32dev": FDLB_F32_DEV}
 
 class fdlb_bc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("pad_", ctypes.c_int32), ("rho", ctypes.c_double),
-                ("ux", ctypes.c_double), ("uy", ctypes.c_double), ("T", ctypes.c_double)]
+                ("ux", ctypes.c_double), ("uy", ctypes.c_double), ("T", ctypes.c_double),
+                ("lo_kind", ctypes.c_int32), ("pad2_", ctypes.c_int32), ("lo_rho", ctypes.c_double),
+                ("lo_ux", ctypes.c_double), ("lo_uy", ctypes.c_double), ("lo_T", ctypes.c_double),
+                ("split", ctypes.c_double), ("split_rate", ctypes.c_double)]
 
 
 class fdlb_params(ctypes.Structure):
@@ -68,6 +71,7 @@ _sigs = {
     "fdlb_set_f": (ctypes.c_int, [_CTX, ctypes.c_void_p, ctypes.c_size_t]),
     "fdlb_diag": (ctypes.c_int, [_CTX, _DP, ctypes.POINTER(ctypes.c_int32)]),
     "fdlb_steps_done": (ctypes.c_int64, [_CTX]),
+    "fdlb_set_clock": (ctypes.c_int, [_CTX, ctypes.c_int64]),
     "fdlb_destroy": (None, [_CTX]),
     "fdlb_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fdlb_last_error": (ctypes.c_char_p, [_CTX]),
@@ -110,7 +114,7 @@ def _ptr(a):
 
 def make_params(prob, precision="f64", tile=0):
     """fdlb_params from a problem dict: nx, ny, dx, dy, dt, tau, lam, v, bc (4 kinds),
-    bc_state (4 x (rho, ux, uy, T))."""
+    bc_state (4 x (rho, ux, uy, T)), lower (4 x None or (kind, state, split, split_rate))."""
     p = fdlb_params()
     p.nx, p.ny = int(prob["nx"]), int(prob["ny"])
     p.dx, p.dy = float(prob["dx"]), float(prob.get("dy", prob["dx"]))
@@ -120,6 +124,12 @@ def make_params(prob, precision="f64", tile=0):
         p.bc[k].kind = int(prob["bc"][k])
         st = prob.get("bc_state", [(1.0, 0.0, 0.0, 1.0)] * 4)[k]
         p.bc[k].rho, p.bc[k].ux, p.bc[k].uy, p.bc[k].T = map(float, st)
+        lo = prob.get("lower", (None,) * 4)[k]
+        if lo is not None:
+            kind, lst, split, rate = lo
+            p.bc[k].lo_kind = int(kind)
+            p.bc[k].lo_rho, p.bc[k].lo_ux, p.bc[k].lo_uy, p.bc[k].lo_T = map(float, lst)
+            p.bc[k].split, p.bc[k].split_rate = float(split), float(rate)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.tile = int(tile)
     return p
@@ -217,6 +227,10 @@ def fdlb_diag(ctx):
 
 def fdlb_steps_done(ctx):
     return int(_lib.fdlb_steps_done(ctx))
+
+
+def fdlb_set_clock(ctx, steps):
+    _check(_lib.fdlb_set_clock(ctx, int(steps)), ctx)
 
 
 def fdlb_destroy(ctx):

@@ -98,6 +98,15 @@ int validate(const fdlb_params &p) {
         if (b.kind == FDLB_BC_DIRICHLET) {
             if (!finite_pos(b.rho) || !finite_pos(b.T) || !std::isfinite(b.ux) || !std::isfinite(b.uy)) return 1;
         }
+        if (b.lo_kind < FDLB_BC_PERIODIC || b.lo_kind > FDLB_BC_WALL) return 1;
+        if (b.lo_kind != FDLB_BC_PERIODIC) {
+            if (b.kind == FDLB_BC_PERIODIC) return 1;  // a periodic side has no segments
+            if (!std::isfinite(b.split) || !std::isfinite(b.split_rate)) return 1;
+            if (b.lo_kind == FDLB_BC_WALL && ((s < 2 && p.nx < 2) || (s >= 2 && p.ny < 2))) return 1;
+            if (b.lo_kind == FDLB_BC_DIRICHLET && (!finite_pos(b.lo_rho) || !finite_pos(b.lo_T) ||
+                                                   !std::isfinite(b.lo_ux) || !std::isfinite(b.lo_uy)))
+                return 1;
+        }
     }
     if ((p.bc[0].kind == FDLB_BC_PERIODIC) != (p.bc[1].kind == FDLB_BC_PERIODIC)) return 1;
     if ((p.bc[2].kind == FDLB_BC_PERIODIC) != (p.bc[3].kind == FDLB_BC_PERIODIC)) return 1;
@@ -163,14 +172,31 @@ void fill_constants(const fdlb_params &p, Inst &I) {
     I.cdy = p.dt / p.dy;
     I.lam = p.lambda;
     for (int s = 0; s < 4; ++s) {
-        I.bc[s] = p.bc[s].kind;
-        I.bcstate[s][0] = p.bc[s].rho;
-        I.bcstate[s][1] = p.bc[s].ux;
-        I.bcstate[s][2] = p.bc[s].uy;
-        I.bcstate[s][3] = p.bc[s].T;
+        const fdlb_bc &b = p.bc[s];
+        I.bc[s] = b.kind;
+        I.bcstate[s][0] = b.rho;
+        I.bcstate[s][1] = b.ux;
+        I.bcstate[s][2] = b.uy;
+        I.bcstate[s][3] = b.T;
+        I.bclo[s] = b.lo_kind;
+        I.bcstate[4 + s][0] = b.lo_rho;
+        I.bcstate[4 + s][1] = b.lo_ux;
+        I.bcstate[4 + s][2] = b.lo_uy;
+        I.bcstate[4 + s][3] = b.lo_T;
+        I.split0[s] = b.lo_kind != FDLB_BC_PERIODIC ? b.split : 0.0;
+        I.split1[s] = b.lo_kind != FDLB_BC_PERIODIC ? b.split_rate : 0.0;
+    }
+    for (int s = 0; s < 8; ++s) {
         I.bcP[s] = 0.0;
         for (int q = 0; q < fdlb::NQ; ++q) I.bcf[s][q] = 0.0;
     }
+}
+
+// A side segment that moves needs the step clock advanced after every step.
+bool moving_sides(const fdlb_params &p) {
+    for (int s = 0; s < 4; ++s)
+        if (p.bc[s].lo_kind != FDLB_BC_PERIODIC && p.bc[s].split_rate != 0.0) return true;
+    return false;
 }
 
 }  // namespace
@@ -189,6 +215,8 @@ struct fdlb_ctx {
     Tile *d_tiles[fdlb::kNumTileKinds] = {nullptr, nullptr, nullptr};
     int ntiles[fdlb::kNumTileKinds] = {0, 0, 0};
     int32_t *d_flag = nullptr;
+    int64_t *d_clock = nullptr;  // steps since the state was set (moving side segments)
+    bool ticks = false;          // some instance has a moving side segment
     double *d_partials = nullptr;
     int nparts = 0;
     double *d_sums = nullptr;
@@ -222,6 +250,7 @@ void release(fdlb_ctx *c) {
     for (auto &t : c->d_tiles)
         if (t) (void)hipFree(t);
     if (c->d_flag) (void)hipFree(c->d_flag);
+    if (c->d_clock) (void)hipFree(c->d_clock);
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_sums) (void)hipFree(c->d_sums);
     delete c;
@@ -294,10 +323,12 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
     c->group = default_group(c->prec);
 
     hipError_t e;
-    if ((e = hipMalloc(&c->d_flag, sizeof(int32_t))) != hipSuccess) {
+    if ((e = hipMalloc(&c->d_flag, sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&c->d_clock, sizeof(int64_t))) != hipSuccess) {
         release(c);
         return FDLB_ENOMEM;
     }
+    for (int i = 0; i < k; ++i) c->ticks = c->ticks || moving_sides(p[i]);
     char *base = static_cast<char *>(arena);
     size_t off = 0;
     c->h_insts.resize(k);
@@ -331,6 +362,7 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
             off += L.w_bytes;
         }
         I.flag = c->d_flag;
+        I.clock = c->d_clock;
         fill_constants(p[i], I);
     }
     int nparts = 0;
@@ -350,7 +382,8 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
     if ((e = hipMemcpyAsync(c->d_insts, c->h_insts.data(), sizeof(Inst) * k, hipMemcpyHostToDevice, c->stream)) !=
             hipSuccess ||
 
-        (e = hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream)) != hipSuccess) {
+        (e = hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->d_clock, 0, sizeof(int64_t), c->stream)) != hipSuccess) {
         fdlb_status s = dev_fail(c, e, "upload");
         release(c);
         return s;
@@ -388,6 +421,7 @@ fdlb_status check_flag(fdlb_ctx *c) {
 // Sets instance i from device fields (4 planes) into the current half.
 fdlb_status set_instance(fdlb_ctx *c, int i, const double *dfields) {
     const fdlb_params &p = c->params[i];
+    HIPCHK(c, hipMemsetAsync(c->d_clock, 0, sizeof(int64_t), c->stream));
     HIPCHK(c, fdlb::launch_fill(c->prec, c->d_insts, i, p.nx, p.ny, dfields, c->half, c->stream));
     HIPCHK(c, fdlb::launch_derive(c->prec, c->d_insts, i, p.nx, p.ny, c->half, c->stream));
     c->is_set[i] = 1;
@@ -431,6 +465,7 @@ fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s) {
         for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
             if (c->ntiles[kd] > 0)
                 HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], c->half, s));
+        if (c->ticks) HIPCHK(c, fdlb::launch_tick(c->d_clock, s));
         c->half ^= 1;
     }
     return FDLB_OK;
@@ -597,6 +632,7 @@ fdlb_status fdlb_set_f(fdlb_ctx *c, const void *host, size_t bytes) {
     fdlb_status ms = copy_m(c, nullptr, src, false);
     if (ms != FDLB_OK) return ms;
     HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_clock, 0, sizeof(int64_t), c->stream));
     HIPCHK(c, fdlb::launch_derive(c->prec, c->d_insts, 0, p.nx, p.ny, c->half, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->is_set[0] = 1;
@@ -622,6 +658,15 @@ fdlb_status fdlb_diag(fdlb_ctx *c, double sums[4], int32_t *nonphys) {
 }
 
 int64_t fdlb_steps_done(const fdlb_ctx *c) { return c ? c->steps : 0; }
+
+fdlb_status fdlb_set_clock(fdlb_ctx *c, int64_t steps) {
+    if (!c || steps < 0) return FDLB_EINVAL;
+    // the value is copied before the call returns (pageable source), so a local is fine
+    HIPCHK(c, hipMemcpyAsync(c->d_clock, &steps, sizeof(steps), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->steps = steps;
+    return FDLB_OK;
+}
 
 fdlb_status fdlb_set_tiling(fdlb_ctx *c, int32_t shape_id, int32_t group) {
     if (!c || shape_id < 1 || shape_id > fdlb::kNumTileShapes || group < 1) return FDLB_EINVAL;

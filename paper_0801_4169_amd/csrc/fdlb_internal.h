@@ -48,9 +48,15 @@ struct Inst {
     float kf[3][2][2][4];    // float copies of k1, k2, k3 (float32 path)
     float kkf[2][2][4];      // k1 + 2 k3, float32 path
     float vf[4], vsf[4];     // float copies of v and vs
-    double bcstate[4][4];    // Dirichlet (rho, ux, uy, T) per side
-    double bcf[4][NQ];       // Dirichlet ghost vectors (values representable in storage)
-    double bcP[4];           // their pressures
+    // Dirichlet data per slot: slots 0..3 the sides, 4..7 their lower segments
+    double bcstate[8][4];    // (rho, ux, uy, T)
+    double bcf[8][NQ];       // ghost vectors (values representable in storage)
+    double bcP[8];           // their pressures
+    // lower segments: ghost cells at centre coordinate (i + 1/2) d < split0 + split1 * t
+    // along side s take condition bclo[s] (BC_PERIODIC: no lower segment)
+    int32_t bclo[4];
+    double split0[4], split1[4];
+    const int64_t *clock;    // steps since the state was set (time of the moving segments)
 };
 
 struct Tile {
@@ -80,6 +86,7 @@ hipError_t launch_moments(int prec, const Inst *insts, int inst, int nx, int ny,
 hipError_t launch_diag(int prec, const Inst *insts, int inst, int nx, int ny, int half, double *partials,
                        int npart_offset, hipStream_t s);
 hipError_t launch_diag_final(const double *partials, int nparts, double *sums, hipStream_t s);
+hipError_t launch_tick(int64_t *clock, hipStream_t s);
 int diag_blocks(int nx, int ny);
 
 }  // namespace fdlb

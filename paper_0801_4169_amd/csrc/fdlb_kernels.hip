@@ -399,14 +399,36 @@ struct Src {
     int dside;
 };
 
-__device__ __forceinline__ Src map_cell(const Inst &I, int x, int y) {
+// Condition of side `side` at position i along it (row on the x sides, column on the y
+// sides) at time t: the side's own or its lower segment's; `slot` receives the Dirichlet
+// slot (4..7 for a lower segment).  Same expressions as the oracle, so the choice is the
+// same bit for bit.
+__device__ __forceinline__ int side_kind(const Inst &I, int side, int i, double t, int &slot) {
+    slot = side;
+    if (I.bclo[side] != BC_PERIODIC) {
+        const double d = side < 2 ? I.dy : I.dx;
+        const double c = ((double)i + 0.5) * d;
+        const double sp = I.split0[side] + I.split1[side] * t;
+        if (c < sp) {
+            slot = 4 + side;
+            return I.bclo[side];
+        }
+    }
+    return I.bc[side];
+}
+
+// Time of the current step for the moving side segments.
+__device__ __forceinline__ double step_time(const Inst &I) { return (double)(*I.clock) * I.dt; }
+
+__device__ __forceinline__ Src map_cell(const Inst &I, int x, int y, double t) {
     Src s{0, 0, -1};
     const int nx = I.nx, ny = I.ny;
     if ((unsigned)x >= (unsigned)nx) {
         const int side = x < 0 ? 0 : 1;
-        const int kind = I.bc[side];
+        int slot;
+        const int kind = side_kind(I, side, y, t, slot);
         if (kind == BC_DIRICHLET) {
-            s.dside = side;
+            s.dside = slot;
         } else if (kind == BC_PERIODIC) {
             x = ((x % nx) + nx) % nx;
         } else if (kind == BC_OUTFLOW) {
@@ -418,9 +440,10 @@ __device__ __forceinline__ Src map_cell(const Inst &I, int x, int y) {
     }
     if ((unsigned)y >= (unsigned)ny) {
         const int side = y < 0 ? 2 : 3;
-        const int kind = I.bc[side];
+        int slot;
+        const int kind = side_kind(I, side, x, t, slot);
         if (kind == BC_DIRICHLET) {
-            if (s.dside < 0) s.dside = side;
+            if (s.dside < 0) s.dside = slot;
         } else if (kind == BC_PERIODIC) {
             y = ((y % ny) + ny) % ny;
         } else if (kind == BC_OUTFLOW) {
@@ -438,23 +461,25 @@ __device__ __forceinline__ Src map_cell(const Inst &I, int x, int y) {
     return s;
 }
 
-// Pressure of the neighbour (x, y) (at most one cell outside the grid).
+// Pressure of the neighbour (x, y) (at most one cell outside the grid) at time t.
 __device__ __forceinline__ double load_P(const Inst &I, const double *__restrict__ P,
-                                         const double *__restrict__ PW, int x, int y) {
+                                         const double *__restrict__ PW, int x, int y, double t) {
     const int nx = I.nx, ny = I.ny;
     if ((unsigned)x >= (unsigned)nx) {
         const int side = x < 0 ? 0 : 1;
-        const int kind = I.bc[side];
         const int yc = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
-        if (kind == BC_DIRICHLET) return I.bcP[side];
+        int slot;
+        const int kind = side_kind(I, side, yc, t, slot);
+        if (kind == BC_DIRICHLET) return I.bcP[slot];
         if (kind == BC_WALL) return PW[side * I.wlen + yc];
         x = kind == BC_PERIODIC ? ((x % nx) + nx) % nx : (x < 0 ? 0 : nx - 1);
     }
     if ((unsigned)y >= (unsigned)ny) {
         const int side = y < 0 ? 2 : 3;
-        const int kind = I.bc[side];
         const int xc = x < 0 ? 0 : (x >= nx ? nx - 1 : x);
-        if (kind == BC_DIRICHLET) return I.bcP[side];
+        int slot;
+        const int kind = side_kind(I, side, xc, t, slot);
+        if (kind == BC_DIRICHLET) return I.bcP[slot];
         if (kind == BC_WALL) return PW[side * I.wlen + xc];
         y = kind == BC_PERIODIC ? ((y % ny) + ny) % ny : (y < 0 ? 0 : ny - 1);
     }
@@ -491,17 +516,19 @@ __device__ __forceinline__ int write_pressures(const Inst &I, const S (&f)[NQ], 
         Mout[3 * I.mplane + y * I.ppitch + x] = T;
     }
     const int bad = nonphysical(I, n, ux, uy, T) ? 1 : 0;
-    if ((x == 0 && I.bc[0] == BC_WALL) || (x == I.nx - 1 && I.bc[1] == BC_WALL)) {
+    // a wall on the side or on its lower segment: the mirror image's pressure
+    auto wall = [&](int side) { return I.bc[side] == BC_WALL || I.bclo[side] == BC_WALL; };
+    if ((x == 0 && wall(0)) || (x == I.nx - 1 && wall(1))) {
         moments_of<1>(I, f, n, jx, jy, E);
         primitive(n, jx, jy, E, ux, uy, T, P);
-        if (x == 0 && I.bc[0] == BC_WALL) PWout[0 * I.wlen + y] = P;
-        if (x == I.nx - 1 && I.bc[1] == BC_WALL) PWout[1 * I.wlen + y] = P;
+        if (x == 0 && wall(0)) PWout[0 * I.wlen + y] = P;
+        if (x == I.nx - 1 && wall(1)) PWout[1 * I.wlen + y] = P;
     }
-    if ((y == 0 && I.bc[2] == BC_WALL) || (y == I.ny - 1 && I.bc[3] == BC_WALL)) {
+    if ((y == 0 && wall(2)) || (y == I.ny - 1 && wall(3))) {
         moments_of<2>(I, f, n, jx, jy, E);
         primitive(n, jx, jy, E, ux, uy, T, P);
-        if (y == 0 && I.bc[2] == BC_WALL) PWout[2 * I.wlen + x] = P;
-        if (y == I.ny - 1 && I.bc[3] == BC_WALL) PWout[3 * I.wlen + x] = P;
+        if (y == 0 && wall(2)) PWout[2 * I.wlen + x] = P;
+        if (y == I.ny - 1 && wall(3)) PWout[3 * I.wlen + x] = P;
     }
     return bad;
 }
@@ -584,8 +611,12 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
 
     // offsets: bytes for INTERIOR / TUBE, elements (with mapping) for EDGE
     Src own;
+    double tnow = 0.0;
     if constexpr (MODE != MODE_EDGE) own = Src{(int)((y * I.fpitch + x) * (int)sizeof(S)), 0, -1};
-    else own = map_cell(I, x, y);
+    else {
+        tnow = step_time(I);
+        own = map_cell(I, x, y, tnow);
+    }
     Src hs[NSLOT];
     int hl[NSLOT];
 #pragma unroll
@@ -608,7 +639,7 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
             hl[j] = ly * LW + lx;
             const int X = tile.x0 + lx - 2, Y = tile.y0 + ly - 2;
             if constexpr (MODE != MODE_EDGE) hs[j] = Src{(int)((Y * I.fpitch + X) * (int)sizeof(S)), 0, -1};
-            else hs[j] = map_cell(I, X, Y);
+            else hs[j] = map_cell(I, X, Y, tnow);
         }
     }
 
@@ -644,10 +675,10 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
         Pyp = Pin[yp * I.ppitch + x];
     } else {
         const double *PWin = I.PW[half];
-        Pxm = load_P(I, Pin, PWin, x - 1, y);
-        Pxp = load_P(I, Pin, PWin, x + 1, y);
-        Pym = load_P(I, Pin, PWin, x, y - 1);
-        Pyp = load_P(I, Pin, PWin, x, y + 1);
+        Pxm = load_P(I, Pin, PWin, x - 1, y, tnow);
+        Pxp = load_P(I, Pin, PWin, x + 1, y, tnow);
+        Pym = load_P(I, Pin, PWin, x, y - 1, tnow);
+        Pyp = load_P(I, Pin, PWin, x, y + 1, tnow);
     }
     const double ax = av_coeff(I.lam, Pxm, P0, Pxp, ux, I.dt, I.dx);
     const double ay = av_coeff(I.lam, Pym, P0, Pyp, uy, I.dt, I.dy);
@@ -1172,8 +1203,12 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
     const GLOBAL_AS double *Min = (const GLOBAL_AS double *)I.M[half];
 
     Src own;
+    double tnow = 0.0;
     if constexpr (MODE != MODE_EDGE) own = Src{y * I.fpitch + x, 0, -1};
-    else own = map_cell(I, x, y);
+    else {
+        tnow = step_time(I);
+        own = map_cell(I, x, y, tnow);
+    }
     Src hs[NSLOT];
     int hl[NSLOT];
 #pragma unroll
@@ -1196,7 +1231,7 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
             hl[j] = ly * LW + lx;
             const int X = tile.x0 + lx - 2, Y = tile.y0 + ly - 2;
             if constexpr (MODE != MODE_EDGE) hs[j] = Src{Y * I.fpitch + X, 0, -1};
-            else hs[j] = map_cell(I, X, Y);
+            else hs[j] = map_cell(I, X, Y, tnow);
         } else if constexpr (MODE != MODE_EDGE) {
             hs[j] = own;  // no halo cell: loads stay unconditional (a load under a branch makes
                           // the compiler wait for every load in flight where the branch joins)
@@ -1416,9 +1451,9 @@ __global__ __launch_bounds__(256) void derive_kernel(const Inst *__restrict__ in
 template <class S>
 __global__ void bc_setup_kernel(Inst *insts, int inst) {
     Inst &I = insts[inst];
-    const int side = threadIdx.x;
-    if (side >= 4) return;
-    if (I.bc[side] != BC_DIRICHLET) {
+    const int side = threadIdx.x;  // Dirichlet slot: sides 0..3, their lower segments 4..7
+    if (side >= 8) return;
+    if ((side < 4 ? I.bc[side] : I.bclo[side - 4]) != BC_DIRICHLET) {
         I.bcP[side] = 0.0;
         return;
     }
@@ -1718,6 +1753,16 @@ hipError_t launch_diag(int prec, const Inst *insts, int inst, int nx, int ny, in
         hipLaunchKernelGGL(diag_kernel<double>, dim3(nb), dim3(kDiagBlock), 0, s, insts, inst, half, p);
     else
         hipLaunchKernelGGL(diag_kernel<float>, dim3(nb), dim3(kDiagBlock), 0, s, insts, inst, half, p);
+    return hipGetLastError();
+}
+
+// Advances the step clock of the moving side segments (one per step, after the step).
+__global__ void tick_kernel(int64_t *clock) {
+    if (threadIdx.x == 0) clock[0] = clock[0] + 1;
+}
+
+hipError_t launch_tick(int64_t *clock, hipStream_t s) {
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, s, clock);
     return hipGetLastError();
 }
 

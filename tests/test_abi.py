@@ -87,3 +87,20 @@ def test_strings_and_tile_shapes():
     assert "non-physical" in B.fdlb_strerror(B.FDLB_ENONPHYS)
     shapes = B.fdlb_tile_shapes()
     assert (32, 8) in shapes and all(tx * ty <= 1024 for tx, ty in shapes)
+
+
+def test_side_segments_are_validated():
+    """A lower segment on a periodic side, or with an invalid Dirichlet state, is rejected;
+    a valid one is accepted."""
+    import fdlb_inputs as fi
+    from paper_0801_4169_amd import _binding as B
+    prob = fi.problem(40, 20, 1e-3, 1e-6, 2e-6, 2.0, ("dirichlet", "outflow", "wall", "dirichlet"),
+                      lower=(None, None, ("dirichlet", (1.0, 0.0, 0.0, 1.0), 0.01, 5.0), None))
+    assert B.fdlb_required_bytes(B.make_params(prob)) > 0
+    bad = fi.problem(40, 20, 1e-3, 1e-6, 2e-6, 2.0, ("periodic", "periodic", "wall", "dirichlet"),
+                     lower=(("wall", (1.0, 0.0, 0.0, 1.0), 0.01, 0.0), None, None, None))
+    assert B.fdlb_required_bytes(B.make_params(bad)) == 0
+    bad = fi.problem(40, 20, 1e-3, 1e-6, 2e-6, 2.0, ("dirichlet", "outflow", "wall", "dirichlet"),
+                     lower=(None, None, ("dirichlet", (-1.0, 0.0, 0.0, 1.0), 0.01, 0.0), None))
+    assert B.fdlb_required_bytes(B.make_params(bad)) == 0
+

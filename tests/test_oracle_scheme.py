@@ -283,3 +283,73 @@ def test_sod_tube_converges_to_exact_solution():
     for k in range(3):
         assert errs[1][k] < 0.8 * errs[0][k] and errs[2][k] < 0.8 * errs[1][k], errs
     assert errs[2][0] < 0.01, errs
+
+
+# --------------------------------------------------------------------------------------
+# Side segments (the double Mach reflection of Sec. 5.2.2): a side whose condition changes
+# at a point that may move with time.
+# --------------------------------------------------------------------------------------
+SEG_STATES = [(1.1, 0.4, -0.1, 0.9), (0.9, -0.2, 0.3, 1.2), (1.0, 0.1, 0.2, 1.1), (1.2, 0.0, -0.3, 0.8)]
+
+
+def _seg_problem(lower, bc=("dirichlet", "outflow", "wall", "dirichlet")):
+    return fi.problem(24, 16, 2e-3, 2e-5, 3e-5, 1.5, bc, SEG_STATES, lower=lower)
+
+
+def test_segment_equal_to_its_side_changes_nothing():
+    """A lower segment with the side's own condition, at any split, leaves every bit as it
+    was."""
+    flds = fi.random_fields(24, 16, seed=5)
+    base = _seg_problem(None)
+    same = _seg_problem(tuple((k, st, 0.013, 0.7) for k, st in zip(base["bc"], SEG_STATES)))
+    a, _ = oracle.run_state(base, flds, 15)
+    b, _ = oracle.run_state(same, flds, 15)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("where", ["below", "beyond"])
+def test_segment_beyond_the_side_replaces_it(where):
+    """A split below every cell centre leaves the side's own condition; one beyond every
+    cell gives the lower condition everywhere, the same as a side of that condition."""
+    flds = fi.random_fields(24, 16, seed=6)
+    lo_kinds = ("wall", "dirichlet", "outflow", "wall")
+    lo_states = [SEG_STATES[(k + 1) % 4] for k in range(4)]
+    split = -1.0 if where == "below" else 1.0
+    seg = _seg_problem(tuple((lo_kinds[k], lo_states[k], split, 0.0) for k in range(4)))
+    ref = _seg_problem(None) if where == "below" else _seg_problem(
+        None, bc=lo_kinds) | {"bc_state": tuple(lo_states)}
+    a, _ = oracle.run_state(seg, flds, 15)
+    b, _ = oracle.run_state(ref, flds, 15)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_moving_segment_restarts_at_its_time():
+    """A moving split: 20 steps equal 8 steps and then 12 more started at step 8 (the time
+    is (step0 + step) dt), and differ from the same split held still."""
+    flds = fi.random_fields(24, 16, seed=7)
+    lower = (None, None, ("dirichlet", SEG_STATES[1], 0.01, 500.0), ("wall", SEG_STATES[0], 0.03, -800.0))
+    p = _seg_problem(lower)
+    f0 = oracle.init_state(p, flds)
+    a, _ = oracle.run_f(p, f0, 20)
+    b, _ = oracle.run_f(p, f0, 8)
+    b, _ = oracle.run_f(p, b, 12, step0=8)
+    assert np.array_equal(a, b)
+    still = _seg_problem((None, None, ("dirichlet", SEG_STATES[1], 0.01, 0.0), ("wall", SEG_STATES[0], 0.03, 0.0)))
+    c, _ = oracle.run_f(still, f0, 20)
+    assert not np.array_equal(a, c)
+
+
+@pytest.mark.slow
+def test_double_mach_reflection_readings():
+    """The double Mach reflection (Sec. 5.2.2, 500 x 200, 750 steps, dt = tau = 1e-5): the
+    paper's Mach-20 shock turns the state non-physical after the first step (as the Mach-20
+    regular reflection does); the same geometry with a Mach-5 shock and lambda = 20 stays
+    physical to the end."""
+    p, f, n = fi.double_mach(lam=20.0)
+    _, bad = oracle.run_state(p, f, 3, nthreads=8)
+    assert bad == 1
+    p, f, n = fi.double_mach(mach=5.0, lam=20.0)
+    (r, _, _, T), bad = oracle.run_state(p, f, n, nthreads=8)
+    assert bad == -1 and r.min() > 0 and T.min() > 0
