@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--ensemble-steps", type=int, default=5000, help="steps of the 256-tube ensemble (0: skip)")
     ap.add_argument("--no-sensitivity", action="store_true",
                     help="skip the perturbed float64 run that measures the flow's own sensitivity")
-    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps of the CPU baseline slice (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps of the CPU baseline slice (0: skip)")
     ap.add_argument("--cpu-rows", type=int, default=256, help="rows of the CPU baseline slice")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (calibrates the HBM "

@@ -1499,12 +1499,32 @@ __global__ __launch_bounds__(256) void moments_kernel(const Inst *__restrict__ i
     out[3 * plane + c] = T;
 }
 
-// Totals of (n, jx, jy, E) per 256-cell block in a fixed tree order; the flag is OR-ed.
+// Totals of (n, jx, jy, E) per 256-cell block; the flag is OR-ed.
 constexpr int kDiagBlock = 256;
+
+// Sum of v[0..3] over a 256-thread block, in a fixed order: an xor butterfly inside each
+// 64-lane wavefront (every lane ends with the same bits, addition being commutative), then
+// the four wavefront sums in order.  The result is valid in thread 0.
+__device__ __forceinline__ void block_sum4(double (&v)[4], double (&red)[4][kDiagBlock / 64]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) v[c] = v[c] + __shfl_xor(v[c], m, 64);
+    const int wave = threadIdx.x / 64;
+    if (threadIdx.x % 64 == 0)
+        for (int c = 0; c < 4; ++c) red[c][wave] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) {
+            double t = red[c][0];
+            for (int w = 1; w < kDiagBlock / 64; ++w) t = t + red[c][w];
+            v[c] = t;
+        }
+}
 template <class S>
 __global__ __launch_bounds__(256) void diag_kernel(const Inst *__restrict__ insts, int inst, int half, double *__restrict__ partials) {
     const Inst &I = insts[inst];
-    __shared__ double red[4][kDiagBlock];
+    __shared__ double red[4][kDiagBlock / 64];
     const long cell = (long)blockIdx.x * kDiagBlock + threadIdx.x;
     const long ncell = (long)I.nx * I.ny;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1519,14 +1539,9 @@ __global__ __launch_bounds__(256) void diag_kernel(const Inst *__restrict__ inst
         primitive(v[0], v[1], v[2], v[3], ux, uy, T, P);
         if (nonphysical(I, v[0], ux, uy, T)) *I.flag = 1;
     }
-    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
-    __syncthreads();
-    for (int w = kDiagBlock / 2; w > 0; w /= 2) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = red[c][threadIdx.x] + red[c][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) partials[4 * (long)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+    block_sum4(v, red);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) partials[4 * (long)blockIdx.x + c] = v[c];
 }
 
 // ---- deviation layout (g planes float32, moment planes float64) ----------------------
@@ -1573,7 +1588,7 @@ __global__ __launch_bounds__(256) void moments_dev_kernel(const Inst *__restrict
 __global__ __launch_bounds__(256) void diag_dev_kernel(const Inst *__restrict__ insts, int inst, int half,
                                                        double *__restrict__ partials) {
     const Inst &I = insts[inst];
-    __shared__ double red[4][kDiagBlock];
+    __shared__ double red[4][kDiagBlock / 64];
     const long cell = (long)blockIdx.x * kDiagBlock + threadIdx.x;
     const long ncell = (long)I.nx * I.ny;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1594,31 +1609,21 @@ __global__ __launch_bounds__(256) void diag_dev_kernel(const Inst *__restrict__ 
         v[3] = n * (T + (ux * ux + uy * uy) / 2.0) + gE;
         if (nonphysical(I, n, ux, uy, T)) *I.flag = 1;
     }
-    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
-    __syncthreads();
-    for (int w = kDiagBlock / 2; w > 0; w /= 2) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = red[c][threadIdx.x] + red[c][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) partials[4 * (long)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+    block_sum4(v, red);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) partials[4 * (long)blockIdx.x + c] = v[c];
 }
 
 __global__ __launch_bounds__(kDiagBlock) void diag_final_kernel(const double *__restrict__ partials, int nparts,
                                                                 double *__restrict__ sums) {
-    // each thread sums a fixed strided subset in order, then a fixed tree: deterministic
-    __shared__ double red[4][kDiagBlock];
+    // each thread sums a fixed strided subset in order, then block_sum4: deterministic
+    __shared__ double red[4][kDiagBlock / 64];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < nparts; i += kDiagBlock)
         for (int c = 0; c < 4; ++c) v[c] = v[c] + partials[4 * (long)i + c];
-    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
-    __syncthreads();
-    for (int w = kDiagBlock / 2; w > 0; w /= 2) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = red[c][threadIdx.x] + red[c][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) sums[threadIdx.x] = red[threadIdx.x][0];
+    block_sum4(v, red);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) sums[c] = v[c];
 }
 
 // ------------------------------------------------------------------------------------
