@@ -1176,16 +1176,46 @@ __device__ __forceinline__ void load_m(const Inst &I, const GLOBAL_AS double *Mi
 // stage's arithmetic to that use and keeps all the LDS operands of all stages alive.
 __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 
-template <int TX, int TY, int UPS>
+// Equilibrium coefficients of the halo cells, one row per field (c0..c4, ux, uy, nF0..4),
+// indexed by halo id: the halo threads keep them here rather than in registers.
+constexpr int kHaloFields = 12;
+
+template <int TX, int TY, int UPS, int NHC>
 struct DevSmem {
     double buf[2][2 * UPS][TY + 4][TX + 4];
     double P[(TY + 4) * (TX + 4)];
+    double hc[kHaloFields][NHC];
 };
+
+// Halo cells a tile kind loads (the tube kind only its x halo).
+template <int TX, int TY, int MODE>
+constexpr int dev_halo_cells() {
+    return 4 * (TX + TY) - (MODE == MODE_TUBE ? 4 * TX : 0);
+}
+
+// f^eq of the pair (qa, qa + 4) of halo cell `h` from the LDS coefficient rows.
+template <int QA, int NH>
+__device__ __forceinline__ void dev_feq_pair_lds(const Inst &I, const double (&hc)[kHaloFields][NH], int h, double &fa,
+                                                 double &fb) {
+    if constexpr (QA == 0) {
+        fa = hc[7][h] * hc[0][h];
+        fb = fa;
+    } else {
+        constexpr int k = qk(QA);
+        const double mag = qdiag(QA) ? I.vs[k] : I.v[k];
+        const double s = s_of<QA, double>(mag, hc[5][h], hc[6][h]);
+        const double s2 = s * s;
+        const double ev = __builtin_fma(__builtin_fma(hc[4][h], s2, hc[2][h]), s2, hc[0][h]);
+        const double od = s * __builtin_fma(hc[3][h], s2, hc[1][h]);
+        fa = hc[8 + k][h] * (ev + od);
+        fb = hc[8 + k][h] * (ev - od);
+    }
+}
 
 // One body for the three tile kinds (side mapping only in EDGE tiles).
 template <int TX, int TY, int MODE, int PD, int UPS>
 __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, const Tile &tile, int half,
-                                              DevSmem<TX, TY, UPS> &sm) {
+                                              DevSmem<TX, TY, UPS, dev_halo_cells<TX, TY, MODE>()> &sm) {
     const Inst &I = insts[tile.inst];
     constexpr int NT = TX * TY;
     constexpr int H0 = MODE == MODE_TUBE ? 4 * TX : 0;  // the tube body loads only the x halo
@@ -1279,20 +1309,34 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
             if (ty < 2) pl[own_l + TY * LW] = v;
         }
     };
-    DevCell dc, dh[NSLOT];
+    DevCell dc;
     {
         double n, ux, uy, T;
         load_m<MODE>(I, Min, own, n, ux, uy, T);
         dev_cell(I, n, ux, uy, T, dc);
         put(sm.P, n * T);
     }
+    constexpr int NH = dev_halo_cells<TX, TY, MODE>();
 #pragma unroll
     for (int j = 0; j < NSLOT; ++j)
         if (MODE != MODE_EDGE || hl[j] >= 0) {
             double n, ux, uy, T;
             load_m<MODE>(I, Min, hs[j], n, ux, uy, T);
-            dev_cell(I, n, ux, uy, T, dh[j]);
-            if (hl[j] >= 0) sm.P[hl[j]] = n * T;
+            if (hl[j] >= 0) {
+                DevCell d;
+                dev_cell(I, n, ux, uy, T, d);
+                const int h = tid + j * NT;  // halo id relative to H0
+                sm.hc[0][h] = d.c0;
+                sm.hc[1][h] = d.c1;
+                sm.hc[2][h] = d.c2;
+                sm.hc[3][h] = d.c3;
+                sm.hc[4][h] = d.c4;
+                sm.hc[5][h] = d.ux;
+                sm.hc[6][h] = d.uy;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) sm.hc[7 + k][h] = d.nF[k];
+                sm.P[hl[j]] = n * T;
+            }
         }
 
     const double omd = 1.0 - I.dtau;
@@ -1324,7 +1368,7 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
                 for (int j = 0; j < NSLOT; ++j)
                     if (hl[j] >= 0) {
                         double ha, hb;
-                        dev_feq_pair<qa>(Is, dh[j], ha, hb);
+                        dev_feq_pair_lds<qa, NH>(Is, sm.hc, tid + j * NT, ha, hb);
                         pa[hl[j]] = ha + static_cast<double>(gh[slot][i][0][j]);
                         if constexpr (qb >= 0) pbuf[hl[j]] = hb + static_cast<double>(gh[slot][i][1][j]);
                     }
@@ -1400,7 +1444,7 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
 template <int TX, int TY, int MODE>
 __global__ __launch_bounds__(TX *TY) void step_kernel_dev(const Inst *__restrict__ insts,
                                                           const Tile *__restrict__ tiles, int ntiles, int half) {
-    __shared__ DevSmem<TX, TY, FDLB_DEV_UPS> sm;
+    __shared__ DevSmem<TX, TY, FDLB_DEV_UPS, dev_halo_cells<TX, TY, MODE>()> sm;
     const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
     step_body_dev<TX, TY, MODE, FDLB_DEV_PREFETCH, FDLB_DEV_UPS>(insts, tile, half, sm);
 }
