@@ -43,7 +43,7 @@ typedef enum {
     FDLB_OK = 0,
     FDLB_EINVAL = 1,   /* bad argument: sizes, non-positive dx/dt/tau, Courant number >= 1,
                           unpaired periodic sides, short buffer, wrong instance index */
-    FDLB_ENOMEM = 2,   /* the library's own small allocation failed */
+    FDLB_ENOMEM = 2,   /* the library's own small allocation failed (hipErrorOutOfMemory) */
     FDLB_EDEVICE = 3,  /* a HIP call failed (the HIP error string is kept, fdlb_last_error) */
     FDLB_ENONPHYS = 4, /* the non-physical flag is set (see above) */
     FDLB_ESTATE = 5    /* call order: stepping or reading before a state was set */
@@ -168,6 +168,10 @@ fdlb_status fdlb_set_clock(fdlb_ctx *c, int64_t steps);
 
 void fdlb_destroy(fdlb_ctx *c);
 const char *fdlb_strerror(fdlb_status s);
+/* The HIP error behind the last FDLB_EDEVICE (or FDLB_ENOMEM) of context c; with c = NULL,
+ * that of the calling thread's last failed fdlb_create / fdlb_batch_create ("" after a
+ * successful one).  The string stays valid until the next call on the same context
+ * (thread). */
 const char *fdlb_last_error(const fdlb_ctx *c);
 
 /* Tile shapes the step kernel is built for: writes up to `cap` (tx, ty) pairs and returns

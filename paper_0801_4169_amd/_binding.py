@@ -20,6 +20,12 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"libfdlb.so not built ({LIB_PATH}); run __graft_entry__.build() or "
                       "python paper_0801_4169_amd/build.py")
 
+# torch carries its own HIP and HSA runtimes.  Loading libfdlb first would bring in the
+# system ones as well, and two HSA runtimes in one process do not share devices or memory
+# (allocations then fail).  With torch loaded first, libfdlb's libamdhip64 dependency
+# resolves by soname to torch's copy, and both use the same runtime.
+import torch  # noqa: E402,F401  (imported for its HIP runtime, before the library)
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 FDLB_OK, FDLB_EINVAL, FDLB_ENOMEM, FDLB_EDEVICE, FDLB_ENONPHYS, FDLB_ESTATE = range(6)
@@ -97,7 +103,7 @@ def fdlb_strerror(status):
 
 def _check(status, ctx=None):
     if status != FDLB_OK:
-        msg = _lib.fdlb_last_error(ctx).decode() if ctx else ""
+        msg = _lib.fdlb_last_error(ctx).decode()
         raise FdlbError(status, msg)
 
 

@@ -235,6 +235,20 @@ fdlb_status dev_fail(fdlb_ctx *c, hipError_t e, const char *what) {
     return FDLB_EDEVICE;
 }
 
+// The last failure of fdlb_create / fdlb_batch_create on this thread (no context exists
+// to hold it); fdlb_last_error(NULL) returns it.
+thread_local std::string g_create_err;
+
+void release(fdlb_ctx *c);
+
+// A failed step of context creation: keeps the HIP error, frees the partial context.
+// hipErrorOutOfMemory is FDLB_ENOMEM, any other HIP error FDLB_EDEVICE.
+fdlb_status create_fail(fdlb_ctx *c, hipError_t e, const char *what) {
+    g_create_err = std::string(what) + ": " + hipGetErrorString(e);
+    release(c);
+    return e == hipErrorOutOfMemory ? FDLB_ENOMEM : FDLB_EDEVICE;
+}
+
 #define HIPCHK(ctx, call)                                          \
     do {                                                           \
         hipError_t e_ = (call);                                    \
@@ -300,6 +314,7 @@ fdlb_status set_tiles(fdlb_ctx *c, int shape, int group) {
 }
 
 fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, size_t bytes, fdlb_ctx **out) {
+    g_create_err.clear();
     if (!out) return FDLB_EINVAL;
     *out = nullptr;
     if (k < 1 || !p || !arena) return FDLB_EINVAL;
@@ -324,10 +339,8 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
 
     hipError_t e;
     if ((e = hipMalloc(&c->d_flag, sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(&c->d_clock, sizeof(int64_t))) != hipSuccess) {
-        release(c);
-        return FDLB_ENOMEM;
-    }
+        (e = hipMalloc(&c->d_clock, sizeof(int64_t))) != hipSuccess)
+        return create_fail(c, e, "hipMalloc");
     for (int i = 0; i < k; ++i) c->ticks = c->ticks || moving_sides(p[i]);
     char *base = static_cast<char *>(arena);
     size_t off = 0;
@@ -368,45 +381,32 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
     int nparts = 0;
     for (int i = 0; i < k; ++i) nparts += fdlb::diag_blocks(p[i].nx, p[i].ny);
     c->nparts = nparts;
-    if (hipMalloc(&c->d_insts, sizeof(Inst) * k) != hipSuccess ||
-        hipMalloc(&c->d_partials, sizeof(double) * 4 * (size_t)nparts) != hipSuccess ||
-        hipMalloc(&c->d_sums, sizeof(double) * 4) != hipSuccess) {
-        release(c);
-        return FDLB_ENOMEM;
-    }
-    if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
-        fdlb_status s = dev_fail(c, e, "hipStreamCreateWithFlags");
-        release(c);
-        return s;
-    }
+    if ((e = hipMalloc(&c->d_insts, sizeof(Inst) * k)) != hipSuccess ||
+        (e = hipMalloc(&c->d_partials, sizeof(double) * 4 * (size_t)nparts)) != hipSuccess ||
+        (e = hipMalloc(&c->d_sums, sizeof(double) * 4)) != hipSuccess)
+        return create_fail(c, e, "hipMalloc");
+    if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return create_fail(c, e, "hipStreamCreateWithFlags");
     if ((e = hipMemcpyAsync(c->d_insts, c->h_insts.data(), sizeof(Inst) * k, hipMemcpyHostToDevice, c->stream)) !=
             hipSuccess ||
 
         (e = hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream)) != hipSuccess ||
-        (e = hipMemsetAsync(c->d_clock, 0, sizeof(int64_t), c->stream)) != hipSuccess) {
-        fdlb_status s = dev_fail(c, e, "upload");
-        release(c);
-        return s;
-    }
+        (e = hipMemsetAsync(c->d_clock, 0, sizeof(int64_t), c->stream)) != hipSuccess)
+        return create_fail(c, e, "upload");
     for (int i = 0; i < k; ++i)
-        if ((e = fdlb::launch_bc_setup(c->prec, c->d_insts, i, c->stream)) != hipSuccess) {
-            fdlb_status s = dev_fail(c, e, "bc_setup");
-            release(c);
-            return s;
-        }
+        if ((e = fdlb::launch_bc_setup(c->prec, c->d_insts, i, c->stream)) != hipSuccess)
+            return create_fail(c, e, "bc_setup");
     {
         fdlb_status ts = set_tiles(c, c->shape, c->group);
         if (ts != FDLB_OK) {
+            g_create_err = c->err.empty() ? "tile table: " + std::string(fdlb_strerror(ts)) : c->err;
             release(c);
             return ts;
         }
     }
     // the descriptors and tile table come from host vectors: finish before they go away
-    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) {
-        fdlb_status s = dev_fail(c, e, "hipStreamSynchronize");
-        release(c);
-        return s;
-    }
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return create_fail(c, e, "hipStreamSynchronize");
+    g_create_err.clear();
     *out = c;
     return FDLB_OK;
 }
@@ -789,7 +789,7 @@ const char *fdlb_strerror(fdlb_status s) {
     }
 }
 
-const char *fdlb_last_error(const fdlb_ctx *c) { return c ? c->err.c_str() : ""; }
+const char *fdlb_last_error(const fdlb_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 int32_t fdlb_tile_shapes(int32_t *tx_ty, int32_t cap) {
     for (int s = 0; s < fdlb::kNumTileShapes && s < cap; ++s) {

@@ -104,3 +104,28 @@ def test_side_segments_are_validated():
                      lower=(None, None, ("dirichlet", (-1.0, 0.0, 0.0, 1.0), 0.01, 0.0), None))
     assert B.fdlb_required_bytes(B.make_params(bad)) == 0
 
+
+
+def test_binding_uses_one_hip_runtime_whatever_the_import_order():
+    """Importing the package before torch still maps a single HIP runtime and a single HSA
+    runtime (two HSA runtimes in one process do not share devices or memory)."""
+    import subprocess
+    import sys
+    code = ("import paper_0801_4169_amd, torch\n"
+            "m = open('/proc/self/maps').read().splitlines()\n"
+            "libs = {l.split()[-1] for l in m if l.split() and l.split()[-1].startswith('/')}\n"
+            "print(sum('libamdhip64' in x for x in libs), sum('libhsa-runtime64' in x for x in libs))\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split()[-2:] == ["1", "1"], r.stdout
+
+
+def test_failed_create_keeps_no_stale_message():
+    """fdlb_last_error(NULL) describes the calling thread's last failed create; a create
+    rejected for its arguments leaves it empty."""
+    from paper_0801_4169_amd import _binding as B
+    prm = _sod_params()
+    with pytest.raises(B.FdlbError) as e:
+        B.fdlb_create(prm, 0, 0x1000, 1)
+    assert e.value.status == B.FDLB_EINVAL
+    assert B._lib.fdlb_last_error(None).decode() == ""
