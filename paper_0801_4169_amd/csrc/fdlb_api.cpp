@@ -121,6 +121,13 @@ int default_group(int prec) {
     return prec == FDLB_F64 ? 16 : 32;
 }
 
+// Captured steps run the tube and edge tiles as a branch beside the interior tiles;
+// FDLB_GRAPH_FORK=0 keeps every kind on one stream.
+bool default_fork() {
+    const char *e = std::getenv("FDLB_GRAPH_FORK");
+    return !(e && std::atoi(e) == 0);
+}
+
 // Tile shape (index into kTileShapes), measured: 64 x 8 for float64, 32 x 8 for float32
 // and the deviation layout; 64 x 4 when the grid is four cells high (one tile spans a
 // tube's periodic height).
@@ -158,6 +165,7 @@ void fill_constants(const fdlb_params &p, Inst &I) {
                 I.k1[al][kind][k] = c / 2.0;
                 I.k2[al][kind][k] = c * c / 2.0;
                 I.k3[al][kind][k] = c * (1.0 - c * c) / 12.0;
+                I.kk[al][kind][k] = std::fma(2.0, I.k3[al][kind][k], I.k1[al][kind][k]);
                 I.kf[0][al][kind][k] = (float)I.k1[al][kind][k];
                 I.kf[1][al][kind][k] = (float)I.k2[al][kind][k];
                 I.kf[2][al][kind][k] = (float)I.k3[al][kind][k];
@@ -211,6 +219,11 @@ struct fdlb_ctx {
     std::vector<Inst> h_insts;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    // side branch of a captured step: the tube and edge tiles run beside the interior
+    // tiles (they read the same half and write disjoint cells)
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool fork = true;
     Inst *d_insts = nullptr;
     Tile *d_tiles[fdlb::kNumTileKinds] = {nullptr, nullptr, nullptr};
     int ntiles[fdlb::kNumTileKinds] = {0, 0, 0};
@@ -260,6 +273,9 @@ void release(fdlb_ctx *c) {
     for (auto &g : c->graph)
         if (g) (void)hipGraphExecDestroy(g);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->d_insts) (void)hipFree(c->d_insts);
     for (auto &t : c->d_tiles)
         if (t) (void)hipFree(t);
@@ -385,8 +401,13 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
         (e = hipMalloc(&c->d_partials, sizeof(double) * 4 * (size_t)nparts)) != hipSuccess ||
         (e = hipMalloc(&c->d_sums, sizeof(double) * 4)) != hipSuccess)
         return create_fail(c, e, "hipMalloc");
-    if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+    if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking)) != hipSuccess)
         return create_fail(c, e, "hipStreamCreateWithFlags");
+    if ((e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess)
+        return create_fail(c, e, "hipEventCreateWithFlags");
+    c->fork = default_fork();
     if ((e = hipMemcpyAsync(c->d_insts, c->h_insts.data(), sizeof(Inst) * k, hipMemcpyHostToDevice, c->stream)) !=
             hipSuccess ||
 
@@ -460,11 +481,24 @@ fdlb_status get_instance_host(fdlb_ctx *c, int i, double *rho, double *ux, doubl
     return check_flag(c);
 }
 
-fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s) {
+// n steps on stream s.  branch: the tube and edge tiles of a step go on the side stream
+// (fork and join through events), in a graph capture a parallel branch beside the interior
+// tiles; without it every kind runs in turn on s.
+fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s, bool branch = false) {
+    branch = branch && c->fork && c->ntiles[0] > 0 && (c->ntiles[1] > 0 || c->ntiles[2] > 0);
     for (int64_t t = 0; t < n; ++t) {
-        for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
+        if (branch) {
+            HIPCHK(c, hipEventRecord(c->ev_fork, s));
+            HIPCHK(c, hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+        }
+        for (int kd = fdlb::kNumTileKinds - 1; kd >= 0; --kd)
             if (c->ntiles[kd] > 0)
-                HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], c->half, s));
+                HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], c->half,
+                                            branch && kd > 0 ? c->side_stream : s));
+        if (branch) {
+            HIPCHK(c, hipEventRecord(c->ev_join, c->side_stream));
+            HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
+        }
         if (c->ticks) HIPCHK(c, fdlb::launch_tick(c->d_clock, s));
         c->half ^= 1;
     }
@@ -478,7 +512,7 @@ fdlb_status ensure_graph(fdlb_ctx *c, int h) {
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
     const int saved = c->half;
     c->half = h;
-    fdlb_status s = launch_steps(c, kGraphSteps, c->cap_stream);
+    fdlb_status s = launch_steps(c, kGraphSteps, c->cap_stream, true);
     c->half = saved;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (s != FDLB_OK) {

@@ -42,6 +42,7 @@ struct Inst {
     double eax[4], edg[4];   // |v|^2 / 2 for axis and diagonal velocities
     double FA[4], FB[4], FC[4], Fden[4]; // weight polynomial constants, Eq. (fk_eq1)
     double k1[2][2][4], k2[2][2][4], k3[2][2][4]; // [alpha][axis=0, diag=1][speed], c >= 0
+    double kk[2][2][4];                           // k1 + 2 k3 (the deviation update's weight)
     double dt, dx, dy, dtau, lam;
     double Fdinv[4];         // 1 / Fden (deviation path, which needs no fixed order)
     double cdx, cdy;         // dt / dx, dt / dy

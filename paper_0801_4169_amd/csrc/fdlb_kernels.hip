@@ -1082,6 +1082,18 @@ __device__ __forceinline__ double av_dev(double lam, double Pm, double P0, doubl
     return th * kap * (1.0 - kap) * 0.5;
 }
 
+// s = v_q . u of the deviation body (a diagonal with one fused multiply-add).
+template <int Q>
+__device__ __forceinline__ double dev_s(const Inst &I, double ux, double uy) {
+    constexpr int k = qk(Q), sx = qsx(Q), sy = qsy(Q);
+    if constexpr (sx != 0 && sy != 0) {
+        const double m = I.vs[k];
+        return __builtin_fma(sx > 0 ? m : -m, ux, (sy > 0 ? m : -m) * uy);
+    } else {
+        return s_of<Q, double>(I.v[k], ux, uy);
+    }
+}
+
 // f^eq of the pair (qa, qa + 4): even and odd powers of s = v . u (qa = 0: the rest value).
 template <int QA>
 __device__ __forceinline__ void dev_feq_pair(const Inst &I, const DevCell &d, double &fa, double &fb) {
@@ -1090,8 +1102,7 @@ __device__ __forceinline__ void dev_feq_pair(const Inst &I, const DevCell &d, do
         fb = fa;
     } else {
         constexpr int k = qk(QA);
-        const double mag = qdiag(QA) ? I.vs[k] : I.v[k];
-        const double s = s_of<QA, double>(mag, d.ux, d.uy);
+        const double s = dev_s<QA>(I, d.ux, d.uy);
         const double s2 = s * s;
         const double ev = __builtin_fma(__builtin_fma(d.c4, s2, d.c2), s2, d.c0);
         const double od = s * __builtin_fma(d.c3, s2, d.c1);
@@ -1114,7 +1125,7 @@ __device__ __forceinline__ double update_dev(const Inst &I, double ax, double ay
     fn = __builtin_fma(I.dtau, feq, fn);
     if constexpr (sx != 0) {
         const double k3 = I.k3[0][dg][k];
-        const double kk = __builtin_fma(2.0, k3, I.k1[0][dg][k]);
+        const double kk = I.kk[0][dg][k];
         fn = __builtin_fma(sx > 0 ? Kx - kk : Kx + kk, xp1, fn);
         fn = __builtin_fma(sx > 0 ? Kx + kk : Kx - kk, xm1, fn);
         fn = __builtin_fma(sx > 0 ? k3 : -k3, xp2 - xm2, fn);
@@ -1123,7 +1134,7 @@ __device__ __forceinline__ double update_dev(const Inst &I, double ax, double ay
     }
     if constexpr (sy != 0) {
         const double k3 = I.k3[1][dg][k];
-        const double kk = __builtin_fma(2.0, k3, I.k1[1][dg][k]);
+        const double kk = I.kk[1][dg][k];
         fn = __builtin_fma(sy > 0 ? Ky - kk : Ky + kk, yp1, fn);
         fn = __builtin_fma(sy > 0 ? Ky + kk : Ky - kk, ym1, fn);
         fn = __builtin_fma(sy > 0 ? k3 : -k3, yp2 - ym2, fn);
@@ -1202,8 +1213,7 @@ __device__ __forceinline__ void dev_feq_pair_lds(const Inst &I, const double (&h
         fb = fa;
     } else {
         constexpr int k = qk(QA);
-        const double mag = qdiag(QA) ? I.vs[k] : I.v[k];
-        const double s = s_of<QA, double>(mag, hc[5][h], hc[6][h]);
+        const double s = dev_s<QA>(I, hc[5][h], hc[6][h]);
         const double s2 = s * s;
         const double ev = __builtin_fma(__builtin_fma(hc[4][h], s2, hc[2][h]), s2, hc[0][h]);
         const double od = s * __builtin_fma(hc[3][h], s2, hc[1][h]);
