@@ -169,8 +169,8 @@ def cpu_baseline(prob, fields, steps, rows):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the slab decomposition over several "
+              "GPUs is not built", file=sys.stderr)
         sys.exit(2)
     import torch
 
