@@ -121,7 +121,7 @@ int default_group(int prec) {
     return prec == FDLB_F64 ? 16 : 32;
 }
 
-// Captured steps run the tube and edge tiles as a branch beside the interior tiles;
+// Captured steps run the smaller tile kinds as a branch beside the largest one;
 // FDLB_GRAPH_FORK=0 keeps every kind on one stream.
 bool default_fork() {
     const char *e = std::getenv("FDLB_GRAPH_FORK");
@@ -219,8 +219,8 @@ struct fdlb_ctx {
     std::vector<Inst> h_insts;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    // side branch of a captured step: the tube and edge tiles run beside the interior
-    // tiles (they read the same half and write disjoint cells)
+    // side branch of a captured step: the smaller tile kinds run beside the largest one
+    // (the kinds read the same half and write disjoint cells)
     hipStream_t side_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool fork = true;
@@ -481,11 +481,16 @@ fdlb_status get_instance_host(fdlb_ctx *c, int i, double *rho, double *ux, doubl
     return check_flag(c);
 }
 
-// n steps on stream s.  branch: the tube and edge tiles of a step go on the side stream
-// (fork and join through events), in a graph capture a parallel branch beside the interior
-// tiles; without it every kind runs in turn on s.
+// n steps on stream s.  branch: the tile kinds other than the largest go on the side
+// stream (fork and join through events), in a graph capture a parallel branch beside the
+// largest kind; without it every kind runs in turn on s.
 fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s, bool branch = false) {
-    branch = branch && c->fork && c->ntiles[0] > 0 && (c->ntiles[1] > 0 || c->ntiles[2] > 0);
+    int main_kd = 0, kinds = 0;
+    for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd) {
+        if (c->ntiles[kd] > 0) ++kinds;
+        if (c->ntiles[kd] > c->ntiles[main_kd]) main_kd = kd;
+    }
+    branch = branch && c->fork && kinds > 1;
     for (int64_t t = 0; t < n; ++t) {
         if (branch) {
             HIPCHK(c, hipEventRecord(c->ev_fork, s));
@@ -494,7 +499,7 @@ fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s, bool branch = fa
         for (int kd = fdlb::kNumTileKinds - 1; kd >= 0; --kd)
             if (c->ntiles[kd] > 0)
                 HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], c->half,
-                                            branch && kd > 0 ? c->side_stream : s));
+                                            branch && kd != main_kd ? c->side_stream : s));
         if (branch) {
             HIPCHK(c, hipEventRecord(c->ev_join, c->side_stream));
             HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
