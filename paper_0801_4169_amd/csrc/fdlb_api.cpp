@@ -121,6 +121,19 @@ int default_group(int prec) {
     return prec == FDLB_F64 ? 16 : 32;
 }
 
+// Edge tiles are cut into pieces of this shape for their launch when it divides the tile
+// shape.  Measured: float64 32 x 4 pieces (its edge kernel holds 225 VGPRs, so smaller
+// workgroups pack beside the other kernel; 2.5% off the 256-tube ensemble step, neutral on
+// the large grid), whole tiles for float32 and deviation storage.  FDLB_EDGE_TILE (a shape
+// id, 1-based; 0 keeps whole tiles) overrides.
+int edge_shape_for(int shape, int prec) {
+    const char *e = std::getenv("FDLB_EDGE_TILE");
+    const int id = e ? std::atoi(e) : (prec == FDLB_F64 ? 7 : 0);
+    if (id < 1 || id > fdlb::kNumTileShapes) return shape;
+    const auto &T = fdlb::kTileShapes[shape], &E = fdlb::kTileShapes[id - 1];
+    return (T.tx % E.tx == 0 && T.ty % E.ty == 0) ? id - 1 : shape;
+}
+
 // Captured steps run the smaller tile kinds as a branch beside the largest one;
 // FDLB_GRAPH_FORK=0 keeps every kind on one stream.
 bool default_fork() {
@@ -214,6 +227,7 @@ struct fdlb_ctx {
     int prec = 0;
     int shape = 0;
     int group = 1;
+    int edge_shape = 0;  // shape of the edge-kind launch (edge tiles cut into pieces of it)
     std::vector<fdlb_params> params;
     std::vector<Layout> layouts;
     std::vector<Inst> h_insts;
@@ -312,6 +326,18 @@ fdlb_status set_tiles(fdlb_ctx *c, int shape, int group) {
                     tiles[fdlb::tile_kind(x0, y0, TX, TY, p.nx, p.ny, p.bc[2].kind)].push_back(Tile{i, x0, y0, 0});
                 }
     }
+    const int es = edge_shape_for(shape, c->prec);
+    if (es != shape) {
+        const int EX = fdlb::kTileShapes[es].tx, EY = fdlb::kTileShapes[es].ty;
+        std::vector<Tile> pieces;
+        for (const Tile &t : tiles[2]) {
+            const fdlb_params &p = c->params[t.inst];
+            for (int dy = 0; dy < TY; dy += EY)
+                for (int dx = 0; dx < TX; dx += EX)
+                    if (t.x0 + dx < p.nx && t.y0 + dy < p.ny) pieces.push_back(Tile{t.inst, t.x0 + dx, t.y0 + dy, 0});
+        }
+        tiles[2] = pieces;
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd) {
         if (c->d_tiles[kd]) (void)hipFree(c->d_tiles[kd]);
@@ -324,6 +350,7 @@ fdlb_status set_tiles(fdlb_ctx *c, int shape, int group) {
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->shape = shape;
+    c->edge_shape = es;
     c->group = group;
     drop_graphs(c);
     return FDLB_OK;
@@ -498,7 +525,7 @@ fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s, bool branch = fa
         }
         for (int kd = fdlb::kNumTileKinds - 1; kd >= 0; --kd)
             if (c->ntiles[kd] > 0)
-                HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], c->half,
+                HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], c->half,
                                             branch && kd != main_kd ? c->side_stream : s));
         if (branch) {
             HIPCHK(c, hipEventRecord(c->ev_join, c->side_stream));
@@ -745,7 +772,7 @@ fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float 
         if (w == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
         for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
             if (c->ntiles[kd] > 0 && (kind < 0 || kd == kind))
-                HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], h,
+                HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], h,
                                             c->stream));
     }
     HIPCHK(c, hipEventRecord(e1, c->stream));
@@ -790,7 +817,7 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
                 if (w == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
                 for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
                     if (c->ntiles[kd] > 0)
-                        HIPCHK(c, fdlb::launch_step(c->prec, c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd],
+                        HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd],
                                                     h, c->stream));
             }
             HIPCHK(c, hipEventRecord(e1, c->stream));

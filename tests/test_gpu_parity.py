@@ -122,6 +122,34 @@ def test_graph_replay_equals_single_launches(P):
     assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("fork,edge_tile", [("0", "0"), ("1", "0"), ("1", "7"), ("1", "5"), ("0", "2")])
+def test_graph_branch_and_edge_pieces_bitwise(P, monkeypatch, fork, edge_tile):
+    """Captured steps with the edge tiles as a parallel branch or serial (FDLB_GRAPH_FORK),
+    and edge tiles launched whole or cut into 32 x 4, 16 x 4 or 64 x 4 pieces
+    (FDLB_EDGE_TILE): every variant equals the oracle bit for bit, through the graphs (96
+    steps) and for a batch of uneven tubes."""
+    monkeypatch.setenv("FDLB_GRAPH_FORK", fork)
+    monkeypatch.setenv("FDLB_EDGE_TILE", edge_tile)
+    say("graph branch", fork, "edge tile", edge_tile, "reflection 200x72, 96 steps")
+    prob, flds = small_case("reflection", nx=200, ny=72)
+    f_gpu, _ = gpu_run(P, prob, flds, 96)
+    f_ref, _ = oracle.run_f(prob, oracle.init_state(prob, flds), 96, nthreads=NTHR)
+    assert_bitwise(f_gpu, f_ref, f"fork {fork} edge tile {edge_tile}")
+    probs = [fi.problem(nx, 4, 2e-3, 2e-5, 3e-5, 1.5, BC_COMBOS["tube"]) for nx in (150, 67, 301)]
+    fields = [fi.random_fields(p["nx"], 4, seed=i) for i, p in enumerate(probs)]
+    b = P.BatchSolver(probs, precision="f64")
+    for i, fl in enumerate(fields):
+        b.set_state(i, *fl)
+    b.step(64)
+    for i, (p, fl) in enumerate(zip(probs, fields)):
+        m = b.moments(i)
+        f_ref, bad = oracle.run_f(p, oracle.init_state(p, fl), 64)
+        assert bad == -1, i
+        for a, r in zip(m, oracle.fields(p, f_ref)):
+            assert np.array_equal(a, r), f"batch instance {i}"
+    b.close()
+
+
 def test_checkpoint_resume_is_bitwise(P):
     say("checkpoint resume")
     prob, flds = small_case("mixed", nx=50, ny=30)
