@@ -122,10 +122,9 @@ int default_group(int prec) {
 }
 
 // Edge tiles are cut into pieces of this shape for their launch when it divides the tile
-// shape.  Measured: float64 32 x 4 pieces (its edge kernel holds 225 VGPRs, so smaller
-// workgroups pack beside the other kernel; 2.5% off the 256-tube ensemble step, neutral on
-// the large grid), whole tiles for float32 and deviation storage.  FDLB_EDGE_TILE (a shape
-// id, 1-based; 0 keeps whole tiles) overrides.
+// shape.  Measured: float64 32 x 4 pieces (0.7% off the large grid's step), whole tiles for
+// float32 and deviation storage.  FDLB_EDGE_TILE (a shape id, 1-based; 0 keeps whole
+// tiles) overrides.
 int edge_shape_for(int shape, int prec) {
     const char *e = std::getenv("FDLB_EDGE_TILE");
     const int id = e ? std::atoi(e) : (prec == FDLB_F64 ? 7 : 0);
@@ -244,6 +243,7 @@ struct fdlb_ctx {
     int32_t *d_flag = nullptr;
     int64_t *d_clock = nullptr;  // steps since the state was set (moving side segments)
     bool ticks = false;          // some instance has a moving side segment
+    int wall_len = 0;            // float64 with a reflecting side: longest such side (wall pass)
     double *d_partials = nullptr;
     int nparts = 0;
     double *d_sums = nullptr;
@@ -385,6 +385,11 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
         (e = hipMalloc(&c->d_clock, sizeof(int64_t))) != hipSuccess)
         return create_fail(c, e, "hipMalloc");
     for (int i = 0; i < k; ++i) c->ticks = c->ticks || moving_sides(p[i]);
+    if (FDLB_STREAM_EDGE && c->prec == FDLB_F64)
+        for (int i = 0; i < k; ++i)
+            for (int sd = 0; sd < 4; ++sd)
+                if (p[i].bc[sd].kind == FDLB_BC_WALL || p[i].bc[sd].lo_kind == FDLB_BC_WALL)
+                    c->wall_len = std::max(c->wall_len, sd < 2 ? p[i].ny : p[i].nx);
     char *base = static_cast<char *>(arena);
     size_t off = 0;
     c->h_insts.resize(k);
@@ -531,6 +536,7 @@ fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s, bool branch = fa
             HIPCHK(c, hipEventRecord(c->ev_join, c->side_stream));
             HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
         }
+        if (c->wall_len > 0) HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - c->half, s));
         if (c->ticks) HIPCHK(c, fdlb::launch_tick(c->d_clock, s));
         c->half ^= 1;
     }
@@ -774,6 +780,8 @@ fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float 
             if (c->ntiles[kd] > 0 && (kind < 0 || kd == kind))
                 HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], h,
                                             c->stream));
+        if (kind < 0 && c->wall_len > 0)
+            HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - h, c->stream));
     }
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));
@@ -819,6 +827,8 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
                     if (c->ntiles[kd] > 0)
                         HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd],
                                                     h, c->stream));
+                if (c->wall_len > 0)
+                    HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - h, c->stream));
             }
             HIPCHK(c, hipEventRecord(e1, c->stream));
             HIPCHK(c, hipEventSynchronize(e1));

@@ -88,6 +88,15 @@ hipError_t launch_diag(int prec, const Inst *insts, int inst, int nx, int ny, in
                        int npart_offset, hipStream_t s);
 hipError_t launch_diag_final(const double *partials, int nparts, double *sums, hipStream_t s);
 hipError_t launch_tick(int64_t *clock, hipStream_t s);
+// Float64 edge tiles run the streaming body (FDLB_STREAM_EDGE=0: the register-resident
+// body, which writes the wall-image pressures itself).
+#ifndef FDLB_STREAM_EDGE
+#define FDLB_STREAM_EDGE 1
+#endif
+// Pressures of the mirror images beside reflecting sides from the distributions of half
+// `half`, for the k instances (maxlen: the longest side); after each float64 step when
+// FDLB_STREAM_EDGE is on.
+hipError_t launch_wall_pressure(const Inst *insts, int k, int maxlen, int half, hipStream_t s);
 int diag_blocks(int nx, int ny);
 
 }  // namespace fdlb

@@ -831,7 +831,9 @@ __device__ __forceinline__ void acc_term(const Inst &I, S v, double &n, double &
 template <class S, int TX, int TY, int MODE, int PD>
 __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts, const Tile &tile, int half,
                                                  StepSmem<S, TX, TY> &sm) {
-    static_assert(MODE == MODE_INTERIOR || MODE == MODE_TUBE, "streaming body");
+    // EDGE: every cell and halo cell goes through the side mapping; the pressures of the
+    // mirror images beside walls are left to wall_pressure_kernel (they need the cell's 33
+    // new values summed in mirrored order).
     constexpr int NT = TX * TY;
     constexpr int H0 = MODE == MODE_TUBE ? 4 * TX : 0;  // the tube body loads only the x halo
     constexpr int NHALL = 4 * (TX + TY);
@@ -844,11 +846,19 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
     const int tx = tid % TX, ty = tid / TX;
     const int x = tile.x0 + tx, y = tile.y0 + ty;
     const int ny = I.ny;
+    const bool valid = MODE != MODE_EDGE || (x < I.nx && y < ny);
     const GLOBAL_AS char *fin = (const GLOBAL_AS char *)(I.f[half]);
     GLOBAL_AS char *fout = (GLOBAL_AS char *)(I.f[1 - half]);
     const size_t pb = (size_t)I.fplane * sizeof(S);
 
-    const Src own{(int)((y * I.fpitch + x) * (int)sizeof(S)), 0, -1};
+    // offsets: bytes for INTERIOR / TUBE, elements (with mapping) for EDGE
+    Src own;
+    double tnow = 0.0;
+    if constexpr (MODE != MODE_EDGE) own = Src{(int)((y * I.fpitch + x) * (int)sizeof(S)), 0, -1};
+    else {
+        tnow = step_time(I);
+        own = map_cell(I, x, y, tnow);
+    }
     Src hs[NSLOT];
     int hl[NSLOT];
 #pragma unroll
@@ -870,7 +880,8 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
             }
             hl[j] = ly * LW + lx;
             const int X = tile.x0 + lx - 2, Y = tile.y0 + ly - 2;
-            hs[j] = Src{(int)((Y * I.fpitch + X) * (int)sizeof(S)), 0, -1};
+            if constexpr (MODE != MODE_EDGE) hs[j] = Src{(int)((Y * I.fpitch + X) * (int)sizeof(S)), 0, -1};
+            else hs[j] = map_cell(I, X, Y, tnow);
         }
     }
 
@@ -892,11 +903,19 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
     static_for<0, PD>([&](auto stc) { load_stage(stc, I, pb); });
 
     // A2: moments of the cell from the previous step; A3: switching function
-    const GLOBAL_AS double *Mc = (const GLOBAL_AS double *)I.M[half] + (y * I.ppitch + x);
+    // (an edge tile's idle threads read their clamped cell; M and f planes share the pitch)
+    const GLOBAL_AS double *Mc =
+        (const GLOBAL_AS double *)I.M[half] + (MODE == MODE_EDGE ? own.off : y * I.ppitch + x);
     const double n = Mc[0], ux = Mc[I.mplane], uy = Mc[2 * I.mplane], T = Mc[3 * I.mplane];
     const double P0 = n * T;
     double Pxm, Pxp, Pym, Pyp;
-    {
+    if constexpr (MODE == MODE_EDGE) {
+        const double *Pin = I.P[half], *PWin = I.PW[half];
+        Pxm = load_P(I, Pin, PWin, x - 1, y, tnow);
+        Pxp = load_P(I, Pin, PWin, x + 1, y, tnow);
+        Pym = load_P(I, Pin, PWin, x, y - 1, tnow);
+        Pyp = load_P(I, Pin, PWin, x, y + 1, tnow);
+    } else {
         const GLOBAL_AS double *Pin = (const GLOBAL_AS double *)I.P[half];
         const GLOBAL_AS double *pc = Pin + (y * I.ppitch + x);
         Pxm = pc[-1];
@@ -919,7 +938,7 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
     make_cell(C, ux, uy, ax, ay, I.dtau, cell);
 
     const int own_l = (ty + 2) * LW + (tx + 2);
-    const uint32_t own_b = (uint32_t)own.off;
+    const uint32_t own_b = MODE != MODE_EDGE ? (uint32_t)own.off : (uint32_t)((y * I.fpitch + x) * (int)sizeof(S));
     auto put = [&](S *pl, S v) {
         pl[own_l] = v;
         if constexpr (MODE == MODE_TUBE) {
@@ -960,15 +979,17 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
         if constexpr (st + PD < NSTAGE) load_stage(std::integral_constant<int, st + PD>{}, Is, pbs);
         if constexpr (qb < 0) {
             const S fn = update(std::integral_constant<int, 0>{}, Is, pa, fa0, static_cast<S>(cell.nF[0] * cell.c0));
-            store_out(reinterpret_cast<GLOBAL_AS S *>(fout + own_b), fn);
+            if (valid) store_out(reinterpret_cast<GLOBAL_AS S *>(fout + own_b), fn);
             acc_term<0>(Is, fn, n2, jx2, jy2, E2);
         } else {
             S fea, feb;
             feq_pair<qa, S>(Is, cell, fea, feb);
             const S fna = update(std::integral_constant<int, qa>{}, Is, pa, fa0, fea);
             const S fnb = update(std::integral_constant<int, qb>{}, Is, pbuf, fb0, feb);
-            store_out(reinterpret_cast<GLOBAL_AS S *>(fout + (size_t)qa * pbs + own_b), fna);
-            store_out(reinterpret_cast<GLOBAL_AS S *>(fout + (size_t)qb * pbs + own_b), fnb);
+            if (valid) {
+                store_out(reinterpret_cast<GLOBAL_AS S *>(fout + (size_t)qa * pbs + own_b), fna);
+                store_out(reinterpret_cast<GLOBAL_AS S *>(fout + (size_t)qb * pbs + own_b), fnb);
+            }
             // ascending q within the speed group: 1..4 as they come, 5..7 held, then 8
             constexpr int j = (st - 1) % 4;
             acc_term<qa>(Is, fna, n2, jx2, jy2, E2);
@@ -987,13 +1008,15 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
     // A6: moments and pressure for the next step, flag (one store per workgroup)
     double ux2, uy2, T2, P2;
     primitive(n2, jx2, jy2, E2, ux2, uy2, T2, P2);
-    GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[1 - half] + (y * I.ppitch + x);
-    Mo[0] = n2;
-    Mo[I.mplane] = ux2;
-    Mo[2 * I.mplane] = uy2;
-    Mo[3 * I.mplane] = T2;
-    ((GLOBAL_AS double *)I.P[1 - half])[y * I.ppitch + x] = P2;
-    const int bad = nonphysical(I, n2, ux2, uy2, T2) ? 1 : 0;
+    if (valid) {
+        GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[1 - half] + (y * I.ppitch + x);
+        Mo[0] = n2;
+        Mo[I.mplane] = ux2;
+        Mo[2 * I.mplane] = uy2;
+        Mo[3 * I.mplane] = T2;
+        ((GLOBAL_AS double *)I.P[1 - half])[y * I.ppitch + x] = P2;
+    }
+    const int bad = valid && nonphysical(I, n2, ux2, uy2, T2) ? 1 : 0;
     if (__syncthreads_or(bad) && tid == 0) *I.flag = 1;
 }
 
@@ -1015,6 +1038,12 @@ template <class S>
 constexpr bool stream_moments() {
     return use_stream<S>();
 }
+// Edge tiles through the streaming body too (float64): the wall-image pressures then come
+// from wall_pressure_kernel after the step.
+template <class S>
+constexpr bool stream_edge() {
+    return use_stream<S>() && FDLB_STREAM_EDGE != 0;
+}
 
 // One kernel per tile kind, so the common interior kernel gets its own (small) register
 // allocation; the host splits the tile table by kind (same rule as tile_kind below).
@@ -1023,7 +1052,7 @@ __global__ __launch_bounds__(TX *TY) void step_kernel(const Inst *__restrict__ i
                                                       int ntiles, int half) {
     __shared__ StepSmem<S, TX, TY> sm;
     const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
-    if constexpr (MODE == MODE_EDGE || !use_stream<S>())
+    if constexpr (!use_stream<S>() || (MODE == MODE_EDGE && !stream_edge<S>()))
         step_body<S, TX, TY, MODE>(insts, tile, half, sm);
     else
         step_body_stream<S, TX, TY, MODE, FDLB_PREFETCH>(insts, tile, half, sm);
@@ -1816,6 +1845,33 @@ hipError_t launch_diag(int prec, const Inst *insts, int inst, int nx, int ny, in
 }
 
 // Advances the step clock of the moving side segments (one per step, after the step).
+// The pressure of the mirror image of each cell beside a reflecting side (a wall on the
+// side or on its lower segment), from the cell's 33 values of half `half` summed in the
+// mirrored order: the same values write_pressures gives.  Block (i, side, instance).
+__global__ __launch_bounds__(256) void wall_pressure_kernel(const Inst *__restrict__ insts, int half) {
+    const Inst &I = insts[blockIdx.z];
+    const int side = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (!(I.bc[side] == BC_WALL || I.bclo[side] == BC_WALL)) return;
+    if (i >= (side < 2 ? I.ny : I.nx)) return;
+    const int x = side == 0 ? 0 : side == 1 ? I.nx - 1 : i;
+    const int y = side == 2 ? 0 : side == 3 ? I.ny - 1 : i;
+    const double *fin = static_cast<const double *>(I.f[half]);
+    const size_t off = (size_t)y * I.fpitch + x;
+    double f[NQ];
+    static_for<0, NQ>([&](auto qc) { f[decltype(qc)::value] = fin[(size_t)decltype(qc)::value * I.fplane + off]; });
+    double n, jx, jy, E, ux, uy, T, P;
+    if (side < 2) moments_of<1>(I, f, n, jx, jy, E);
+    else moments_of<2>(I, f, n, jx, jy, E);
+    primitive(n, jx, jy, E, ux, uy, T, P);
+    I.PW[half][side * I.wlen + i] = P;
+}
+
+hipError_t launch_wall_pressure(const Inst *insts, int k, int maxlen, int half, hipStream_t s) {
+    hipLaunchKernelGGL(wall_pressure_kernel, dim3((maxlen + 255) / 256, 4, k), dim3(256), 0, s, insts, half);
+    return hipGetLastError();
+}
+
 __global__ void tick_kernel(int64_t *clock) {
     if (threadIdx.x == 0) clock[0] = clock[0] + 1;
 }
