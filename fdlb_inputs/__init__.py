@@ -195,6 +195,23 @@ def paper_tube(name, ny=4):
     return p, riemann_fields(nx, ny, L, R), steps
 
 
+# Sec. 4, Fig. 3: two equal gases meeting at 10 (caption); speeds, dx, dt and tau of Fig. 2
+FIG3_L = (10.0, 10.0, 0.0, 5.0)
+FIG3_R = (10.0, 0.0, 0.0, 5.0)
+
+
+def fig3_tube(t=0.02, lines=15, ny=4):
+    """(problem, fields, steps) of the tube of Fig. 3 (Sec. 4): the caption's states and
+    lambda = 2, with the speeds, dx = 3e-3 and dt = tau = 1e-5 of Fig. 2.  ``lines`` are
+    the terms of Eq. (dis_eq1) kept (15: all; 11: without the dispersion term, line III).
+    The domain [0, 1] (334 cells, jump at the middle) and the end time are not stated
+    (reading: t = 0.02, before the shocks reach the ends)."""
+    nx = 334
+    p = problem(nx, ny, 3e-3, 1e-5, 1e-5, 2.0, TUBE_BC, name=f"fig3_lines{lines}_{nx}x{ny}")
+    p["lines"] = int(lines)
+    return p, riemann_fields(nx, ny, FIG3_L, FIG3_R), int(round(t / 1e-5))
+
+
 def colella_tube(nx=4000, ny=4, dx=2.5e-4, dt=1e-6, tau=2e-6, lam=20.0):
     """Colella's explosion problem (Sec. 5.1.4 states, pressure ratio 1e5) on 4000 x 4,
     20000 steps to t = 0.02."""

@@ -103,6 +103,11 @@ typedef struct {
     fdlb_bc bc[4];       /* x-, x+, y-, y+ */
     int32_t precision;   /* fdlb_precision */
     int32_t tile;        /* tile shape id (fdlb_tile_shapes); 0 = library default (measured) */
+    int32_t lines;       /* terms of Eq. (dis_eq1) kept: bit 0..3 = lines I..IV (central
+                            difference, Lax-Wendroff dissipation, dispersion, artificial
+                            viscosity); 0 or 15 = the full scheme.  Sec. 4 and Fig. 3 study
+                            the scheme with lines left out; the BGK term is always kept. */
+    int32_t pad_;
 } fdlb_params;
 
 /* Bytes of device memory a context for these parameters borrows (both ping-pong halves:

@@ -96,9 +96,11 @@ def _vec(v):
     return np.ascontiguousarray(np.asarray(v, dtype=np.float64))
 
 
-def params(prob, lines=15, theta_fixed=False, theta_value=0.0, step0=0):
+def params(prob, lines=None, theta_fixed=False, theta_value=0.0, step0=0):
     """ctypes parameter block from a problem dict (see ``fdlb_inputs.problem``); ``step0``
-    is the step number of the first step (time-dependent side segments)."""
+    is the step number of the first step (time-dependent side segments); ``lines`` the
+    terms of Eq. (dis_eq1) kept (bits for lines I..IV), by default the problem's own
+    (``prob["lines"]``, else the full scheme)."""
     p = Params()
     p.nx, p.ny = prob["nx"], prob["ny"]
     p.dx, p.dy, p.dt, p.tau, p.lam = prob["dx"], prob["dy"], prob["dt"], prob["tau"], prob["lam"]
@@ -107,7 +109,7 @@ def params(prob, lines=15, theta_fixed=False, theta_value=0.0, step0=0):
         p.bc[k] = prob["bc"][k]
         for c in range(4):
             p.bc_state[k][c] = prob["bc_state"][k][c]
-    p.lines = lines
+    p.lines = int(prob.get("lines", 15)) if lines is None else lines
     p.theta_fixed = 1 if theta_fixed else 0
     p.theta_value = theta_value
     for k, seg in enumerate(prob.get("lower", (None,) * 4)):

@@ -82,6 +82,7 @@ int validate(const fdlb_params &p) {
     if (!std::isfinite(p.lambda) || p.lambda < 0.0) return 1;
     if (p.precision != FDLB_F64 && p.precision != FDLB_F32 && p.precision != FDLB_F32_DEV) return 1;
     if (p.tile < 0 || p.tile > fdlb::kNumTileShapes) return 1;
+    if (p.lines < 0 || p.lines > 15) return 1;
     double vmax = 0.0;
     for (int k = 0; k < 4; ++k) {
         if (!finite_pos(p.v[k])) return 1;
@@ -168,15 +169,18 @@ void fill_constants(const fdlb_params &p, Inst &I) {
         I.Fden[k] = vk2 * (vk2 - a) * (vk2 - b) * (vk2 - d);
         I.Fdinv[k] = 1.0 / I.Fden[k];
     }
+    // a line left out of Eq. (dis_eq1) keeps its place in the sum with a zero weight (adding
+    // zero changes no value, so the float64 path still matches the oracle's sum without it)
+    const int lines = p.lines == 0 ? 15 : p.lines;
     for (int al = 0; al < 2; ++al) {
         const double dr = al == 0 ? p.dx : p.dy;
         for (int kind = 0; kind < 2; ++kind)
             for (int k = 0; k < 4; ++k) {
                 const double mag = kind == 0 ? I.v[k] : I.vs[k];
                 const double c = mag * p.dt / dr;
-                I.k1[al][kind][k] = c / 2.0;
-                I.k2[al][kind][k] = c * c / 2.0;
-                I.k3[al][kind][k] = c * (1.0 - c * c) / 12.0;
+                I.k1[al][kind][k] = (lines & 1) ? c / 2.0 : 0.0;
+                I.k2[al][kind][k] = (lines & 2) ? c * c / 2.0 : 0.0;
+                I.k3[al][kind][k] = (lines & 4) ? c * (1.0 - c * c) / 12.0 : 0.0;
                 I.kk[al][kind][k] = std::fma(2.0, I.k3[al][kind][k], I.k1[al][kind][k]);
                 I.kf[0][al][kind][k] = (float)I.k1[al][kind][k];
                 I.kf[1][al][kind][k] = (float)I.k2[al][kind][k];
@@ -190,7 +194,7 @@ void fill_constants(const fdlb_params &p, Inst &I) {
     I.dtau = p.dt / p.tau;
     I.cdx = p.dt / p.dx;
     I.cdy = p.dt / p.dy;
-    I.lam = p.lambda;
+    I.lam = (lines & 8) ? p.lambda : 0.0;
     for (int s = 0; s < 4; ++s) {
         const fdlb_bc &b = p.bc[s];
         I.bc[s] = b.kind;

@@ -54,7 +54,8 @@ def test_required_bytes_layout():
 
 
 @pytest.mark.parametrize("field,value", [("nx", 0), ("dt", 0.0), ("tau", -1.0), ("dx", float("nan")),
-                                         ("dt", 1.0), ("precision", 7), ("tile", 99), ("lambda_", -1.0)])
+                                         ("dt", 1.0), ("precision", 7), ("tile", 99), ("lambda_", -1.0),
+                                         ("lines", 16), ("lines", -1)])
 def test_invalid_parameters_are_rejected(field, value):
     from paper_0801_4169_amd import _binding as B
     assert B.fdlb_required_bytes(_sod_params(**{field: value})) == 0

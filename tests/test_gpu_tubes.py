@@ -78,3 +78,24 @@ def test_paper_tube(P, name):
                float(np.mean(np.abs(u - ref[1][0])) / np.max(np.abs(ref[1][0]))),
                float(np.sum(np.abs(T - ref[3][0])) / np.sum(ref[3][0])))
         assert all(e <= b for e, b in zip(err, bounds)), (name, prec, err)
+
+
+@pytest.mark.parametrize("lines,nsteps", [(15, None), (11, None), (13, None), (7, 50)])
+def test_fig3_tube_with_lines_left_out_bitwise(P, lines, nsteps):
+    """The Fig. 3 tube (Sec. 4) with all of Eq. (dis_eq1) and with line III (11), line II
+    (13) or line IV (7) left out: float64 equals the oracle's run of the same scheme bit for
+    bit over the 2000 steps (a left-out line is a zero weight on the GPU, a skipped term in
+    the oracle).  Without the artificial viscosity the scheme turns non-physical at step 59,
+    so that case runs 50 steps."""
+    p, f, steps = fi.fig3_tube(lines=lines)
+    steps = nsteps or steps
+    say("fig3 tube, lines", lines, steps, "steps")
+    s = P.Solver(p, precision="f64")
+    s.set_state(*f)
+    s.step(steps)
+    f_gpu = s.get_f(allow_nonphys=True)
+    s.close()
+    f_ref, _ = oracle.run_f(p, oracle.init_state(p, f), steps, nthreads=NTHR)
+    if not np.array_equal(f_gpu, f_ref):
+        n = int(np.count_nonzero(f_gpu != f_ref))
+        raise AssertionError(f"lines {lines}: {n} of {f_ref.size} values differ")
