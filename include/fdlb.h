@@ -221,6 +221,9 @@ fdlb_status fdlb_batch_set_state(fdlb_ctx *c, int32_t i, const double *rho, cons
                                  const double *uy, const double *T);
 fdlb_status fdlb_batch_get_moments(fdlb_ctx *c, int32_t i, double *rho, double *ux, double *uy,
                                    double *T);
+/* nsteps steps of every instance (Eq. dis_eq1), enqueued: the same as fdlb_step on a batch
+ * context, under the batch family's name.  FDLB_ESTATE before every instance has a state. */
+fdlb_status fdlb_batch_step(fdlb_ctx *c, int64_t nsteps);
 
 #ifdef __cplusplus
 }

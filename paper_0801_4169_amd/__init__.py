@@ -186,7 +186,7 @@ class BatchSolver:
         B.fdlb_batch_set_state(self.ctx, i, rho, ux, uy, T, ny * nx)
 
     def step(self, n=1):
-        B.fdlb_step(self.ctx, n)
+        B.fdlb_batch_step(self.ctx, n)
 
     def moments(self, i, allow_nonphys=False):
         ny, nx = self.sizes[i]

@@ -69,6 +69,7 @@ _sigs = {
     "fdlb_set_state_device": (ctypes.c_int, [_CTX, ctypes.c_void_p]),
     "fdlb_batch_set_state": (ctypes.c_int, [_CTX, ctypes.c_int32, _DP, _DP, _DP, _DP]),
     "fdlb_step": (ctypes.c_int, [_CTX, ctypes.c_int64]),
+    "fdlb_batch_step": (ctypes.c_int, [_CTX, ctypes.c_int64]),
     "fdlb_get_moments": (ctypes.c_int, [_CTX, _DP, _DP, _DP, _DP]),
     "fdlb_batch_get_moments": (ctypes.c_int, [_CTX, ctypes.c_int32, _DP, _DP, _DP, _DP]),
     "fdlb_get_moments_device": (ctypes.c_int, [_CTX, ctypes.c_void_p]),
@@ -183,6 +184,10 @@ def fdlb_batch_set_state(ctx, i, rho, ux, uy, T, n):
 
 def fdlb_step(ctx, nsteps):
     _check(_lib.fdlb_step(ctx, int(nsteps)), ctx)
+
+
+def fdlb_batch_step(ctx, nsteps):
+    _check(_lib.fdlb_batch_step(ctx, int(nsteps)), ctx)
 
 
 def _get4(fn, ctx, n, *lead):

@@ -632,6 +632,8 @@ fdlb_status fdlb_step(fdlb_ctx *c, int64_t nsteps) {
     return FDLB_OK;
 }
 
+fdlb_status fdlb_batch_step(fdlb_ctx *c, int64_t nsteps) { return fdlb_step(c, nsteps); }
+
 fdlb_status fdlb_get_moments(fdlb_ctx *c, double *rho, double *ux, double *uy, double *T) {
     if (!c || c->k != 1) return FDLB_EINVAL;
     return get_instance_host(c, 0, rho, ux, uy, T);

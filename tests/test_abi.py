@@ -21,7 +21,7 @@ def test_header_declares_the_hot_path_calls():
     names = declared_functions()
     for n in ("fdlb_create", "fdlb_set_state", "fdlb_step", "fdlb_get_moments", "fdlb_destroy",
               "fdlb_batch_create", "fdlb_batch_set_state", "fdlb_batch_get_moments", "fdlb_get_f", "fdlb_set_f",
-              "fdlb_diag", "fdlb_required_bytes"):
+              "fdlb_diag", "fdlb_required_bytes", "fdlb_batch_step"):
         assert n in names
 
 
