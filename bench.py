@@ -34,7 +34,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # the deviation storage
 ALG_BYTES = {"f64": 2 * 33 * 8, "f32": 2 * 33 * 4, "f32dev": 2 * (33 * 4 + 4 * 8)}
 KERNEL_SRC = os.path.join(ROOT, "paper_0801_4169_amd", "csrc", "fdlb_kernels.hip")
-COUNTERS = os.path.join(ROOT, "profiles", "step_interior_f64_reflection_8192x2048_counters.md")
+# counter summaries of the interior kernel per storage (rocprofv3 FETCH_SIZE / WRITE_SIZE)
+COUNTERS = {pr: os.path.join(ROOT, "profiles", f"step_interior_{pr}_reflection_8192x2048_counters.md")
+            for pr in ("f64", "f32", "f32dev")}
 
 
 def parse():
@@ -63,12 +65,13 @@ def src_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def committed_traffic():
-    """HBM bytes per interior-kernel launch from the committed counter summary, if it was
-    taken on the current kernel source."""
-    if not os.path.exists(COUNTERS):
+def committed_traffic(precision="f64"):
+    """HBM bytes per interior-kernel launch of a storage from its committed counter summary,
+    if it was taken on the current kernel source."""
+    path = COUNTERS[precision]
+    if not os.path.exists(path):
         return None
-    text = open(COUNTERS).read()
+    text = open(path).read()
     h = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]+)", text)
     b = re.search(r"traffic bytes per launch: ([0-9.eE+]+)", text)
     if not h or not b or h.group(1) != src_hash():
@@ -197,7 +200,7 @@ def main():
     r = res[main_p]
     ms_step = r["ms"] / args.steps
     achieved = ALG_BYTES[main_p] * r["k_cells"] / (r["k_ms"] / 1e3) / 1e9
-    traffic = committed_traffic() if main_p == "f64" else None
+    traffic = committed_traffic(main_p)
     out = {
         "metric": "Mcell-updates/s FP32 vs FP64 at stated L1 error; % of HBM roofline",
         "value": r["rate"] / 1e6,
@@ -238,6 +241,8 @@ def main():
                "hbm_frac": ALG_BYTES[pr] * cells / (o["ms"] / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS,
                "kernel_ms": o["k_ms"],
                "kernel_hbm_frac": ALG_BYTES[pr] * o["k_cells"] / (o["k_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+               "kernel_traffic_gbs": (None if committed_traffic(pr) is None
+                                      else committed_traffic(pr) / (o["k_ms"] / 1e3) / 1e9),
                "speedup_vs_f64": o["rate"] / res["f64"]["rate"], "nonphysical": bool(o["flag"]),
                "tiling": list(o["tiling"])}
         if "f64" in res:
