@@ -96,13 +96,15 @@ def timed_run(P, prob, fields, precision, steps, warmup, tile):
     # the dominant kernel (interior tiles) alone, HIP events on the same stream
     k_ms = P.B.fdlb_time_kernel(s.ctx, 0, 50)
     k_cells = P.B.fdlb_tile_cells(s.ctx, 0)
+    # the practical ceiling: a plain copy of the stored planes over the same tiles
+    copy_ms = P.B.fdlb_copy_ceiling(s.ctx, 50)
     tiling = s.tiling
     m = s.moments(allow_nonphys=True)
     _, flag = s.diag()
     s.close()
     del s
     torch.cuda.empty_cache()
-    return dict(ms=ms, moments=m, flag=flag, k_ms=k_ms, k_cells=k_cells, tiling=tiling)
+    return dict(ms=ms, moments=m, flag=flag, k_ms=k_ms, k_cells=k_cells, tiling=tiling, copy_ms=copy_ms)
 
 
 def l1_rel(a, b):
@@ -224,7 +226,12 @@ def main():
                                 "f32": "fdlb::step_kernel<float, interior tiles>",
                                 "f32dev": "fdlb::step_kernel_dev<interior tiles>"}[main_p],
                      "kernel_ms": r["k_ms"], "kernel_cells": r["k_cells"],
-                     "alg_bytes_per_cell_update": ALG_BYTES[main_p]},
+                     "alg_bytes_per_cell_update": ALG_BYTES[main_p],
+                     # a plain copy of the same planes over the same tiles: the practical
+                     # bandwidth of this access pattern, and the kernel's time against it
+                     "copy_ceiling": {"ms": r["copy_ms"],
+                                      "GBps": ALG_BYTES[main_p] * r["k_cells"] / (r["copy_ms"] / 1e3) / 1e9,
+                                      "kernel_over_copy": r["copy_ms"] / r["k_ms"]}},
         "nonphysical": bool(r["flag"]),
     }
     if "f64" in res and len(precs) > 1 and not args.no_sensitivity:
@@ -243,6 +250,7 @@ def main():
                "kernel_hbm_frac": ALG_BYTES[pr] * o["k_cells"] / (o["k_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
                "kernel_traffic_gbs": (None if committed_traffic(pr) is None
                                       else committed_traffic(pr) / (o["k_ms"] / 1e3) / 1e9),
+               "copy_ceiling_ms": o["copy_ms"], "kernel_over_copy": o["copy_ms"] / o["k_ms"],
                "speedup_vs_f64": o["rate"] / res["f64"]["rate"], "nonphysical": bool(o["flag"]),
                "tiling": list(o["tiling"])}
         if "f64" in res:

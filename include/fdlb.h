@@ -205,6 +205,13 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
  * the autotuner's trial steps).  Syncs. */
 int64_t fdlb_tile_cells(const fdlb_ctx *c, int32_t kind);
 fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float *ms_per_launch);
+/* The practical bandwidth ceiling of the interior kernel: times `launches` launches of a
+ * plain copy of every stored distribution plane (33 planes; the g planes in deviation
+ * storage) over the interior tiles, from the current half to the other, with the step's
+ * tile shape, dispatch order and stores, but no halo, no moment planes and no arithmetic.
+ * The state is not advanced (the other half is overwritten, as by the autotuner's trial
+ * steps).  FDLB_EINVAL without interior tiles; requires a state (FDLB_ESTATE).  Syncs. */
+fdlb_status fdlb_copy_ceiling(fdlb_ctx *c, int32_t launches, float *ms_per_launch);
 
 /* ---- Batched ensembles ------------------------------------------------------------- */
 /* k independent problems of possibly different size and parameters advanced together:

@@ -87,6 +87,7 @@ _sigs = {
     "fdlb_get_tiling": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "fdlb_tile_cells": (ctypes.c_int64, [_CTX, ctypes.c_int32]),
     "fdlb_time_kernel": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "fdlb_copy_ceiling": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
     "fdlb_autotune": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
 }
@@ -279,6 +280,12 @@ def fdlb_time_kernel(ctx, kind, launches):
     ms = ctypes.c_float(0)
     _check(_lib.fdlb_time_kernel(ctx, int(kind), int(launches), ctypes.byref(ms)), ctx)
     return ms.value
+
+
+def fdlb_copy_ceiling(ctx, launches):
+    ms = ctypes.c_float(0.0)
+    _check(_lib.fdlb_copy_ceiling(ctx, int(launches), ctypes.byref(ms)), ctx)
+    return float(ms.value)
 
 
 def fdlb_tile_shapes():

@@ -799,6 +799,28 @@ fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float 
     return FDLB_OK;
 }
 
+fdlb_status fdlb_copy_ceiling(fdlb_ctx *c, int32_t launches, float *ms_per_launch) {
+    if (!c || !ms_per_launch || launches < 1) return FDLB_EINVAL;
+    if (!c->state_set) return FDLB_ESTATE;
+    if (c->ntiles[0] == 0) return FDLB_EINVAL;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const int h = c->half;
+    for (int w = 0; w < 2 + launches; ++w) {
+        if (w == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
+        HIPCHK(c, fdlb::launch_plane_copy(c->prec, c->shape, c->d_insts, c->d_tiles[0], c->ntiles[0], h, c->stream));
+    }
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = ms / (float)launches;
+    return FDLB_OK;
+}
+
 fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape_ids, int32_t nshapes,
                           const int32_t *groups, int32_t ngroups, float *best_ms) {
     if (!c || trial_steps < 1 || nshapes < 0 || ngroups < 0) return FDLB_EINVAL;

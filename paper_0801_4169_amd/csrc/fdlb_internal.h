@@ -78,6 +78,9 @@ constexpr int kNumTileKinds = 3;
 hipError_t launch_step(int prec, int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
                        hipStream_t s);
 int tile_kind(int x0, int y0, int tx, int ty, int nx, int ny, int bc_y);
+// Plain copy of the stored planes of `tiles` (interior tiles) from half `half` to the other.
+hipError_t launch_plane_copy(int prec, int shape, const Inst *insts, const Tile *tiles, int ntiles, int half,
+                             hipStream_t s);
 hipError_t launch_bc_setup(int prec, Inst *insts, int inst, hipStream_t s);
 hipError_t launch_fill(int prec, const Inst *insts, int inst, int nx, int ny, const double *fields, int half,
                        hipStream_t s);

@@ -1771,6 +1771,60 @@ static hipError_t launch_step_p(int shape, int kind, const Inst *insts, const Ti
     }
 }
 
+// ------------------------------------------------------------------------------------
+// Bandwidth reference: every stored plane of the interior tiles copied from half `half`
+// to the other half, one thread per cell as in the step, in the same tile order and
+// XCD-aware remap, batches of planes in flight, non-temporal stores.  No halo, no moment
+// planes, no arithmetic: the practical ceiling of the step's compulsory f traffic.
+// ------------------------------------------------------------------------------------
+template <class S, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void plane_copy_kernel(const Inst *__restrict__ insts,
+                                                            const Tile *__restrict__ tiles, int ntiles, int half) {
+    const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
+    const Inst &I = insts[tile.inst];
+    const int x = tile.x0 + (int)threadIdx.x % TX, y = tile.y0 + (int)threadIdx.x / TX;
+    const GLOBAL_AS S *in = (const GLOBAL_AS S *)(I.f[half]) + ((size_t)y * I.fpitch + x);
+    GLOBAL_AS S *out = (GLOBAL_AS S *)(I.f[1 - half]) + ((size_t)y * I.fpitch + x);
+    constexpr int B = 11;  // planes in flight per thread (33 = 3 x 11)
+    for (int q0 = 0; q0 < NQ; q0 += B) {
+        S v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) v[k] = in[(size_t)(q0 + k) * I.fplane];
+#pragma unroll
+        for (int k = 0; k < B; ++k) store_out(out + (size_t)(q0 + k) * I.fplane, v[k]);
+    }
+}
+
+template <class S, int SHAPE>
+static hipError_t launch_copy_s(const Inst *insts, const Tile *tiles, int ntiles, int half, hipStream_t s) {
+    constexpr int TX = kTileShapes[SHAPE].tx, TY = kTileShapes[SHAPE].ty;
+    hipLaunchKernelGGL((plane_copy_kernel<S, TX, TY>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles, ntiles, half);
+    return hipGetLastError();
+}
+
+template <class S>
+static hipError_t launch_copy_p(int shape, const Inst *insts, const Tile *tiles, int ntiles, int half,
+                                hipStream_t s) {
+    switch (shape) {
+    case 0: return launch_copy_s<S, 0>(insts, tiles, ntiles, half, s);
+    case 1: return launch_copy_s<S, 1>(insts, tiles, ntiles, half, s);
+    case 2: return launch_copy_s<S, 2>(insts, tiles, ntiles, half, s);
+    case 3: return launch_copy_s<S, 3>(insts, tiles, ntiles, half, s);
+    case 4: return launch_copy_s<S, 4>(insts, tiles, ntiles, half, s);
+    case 5: return launch_copy_s<S, 5>(insts, tiles, ntiles, half, s);
+    case 6: return launch_copy_s<S, 6>(insts, tiles, ntiles, half, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_plane_copy(int prec, int shape, const Inst *insts, const Tile *tiles, int ntiles, int half,
+                             hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    // the deviation layout's g planes are float32 like the float32 layout's f planes
+    if (prec == PREC_F64) return launch_copy_p<double>(shape, insts, tiles, ntiles, half, s);
+    return launch_copy_p<float>(shape, insts, tiles, ntiles, half, s);
+}
+
 hipError_t launch_step(int prec, int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
                        hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;

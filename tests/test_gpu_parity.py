@@ -284,6 +284,30 @@ def test_batch_equals_single_runs(P):
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32dev"])
+def test_copy_ceiling_and_kernel_timing_leave_the_state(P, precision):
+    """The bandwidth reference (a plain copy of the stored planes) and the kernel timing
+    write only the other half: the state and the following steps are unchanged."""
+    say("copy ceiling", precision)
+    prob, flds = small_case("reflection", nx=300, ny=70)
+    a = P.Solver(prob, precision=precision)
+    a.set_state(*flds)
+    a.step(5)
+    f0 = a.get_f()
+    assert P.B.fdlb_copy_ceiling(a.ctx, 3) > 0 and P.B.fdlb_time_kernel(a.ctx, -1, 2) > 0
+    f1 = a.get_f()
+    same = (lambda x, y: all(np.array_equal(u, v) for u, v in zip(x, y))) if precision == "f32dev" \
+        else np.array_equal
+    assert same(f0, f1)
+    a.step(7)
+    b = P.Solver(prob, precision=precision)
+    b.set_state(*flds)
+    b.step(12)
+    assert same(a.get_f(), b.get_f())
+    a.close()
+    b.close()
+
+
 def test_autotune_leaves_state_and_results_unchanged(P):
     """The autotuner's trial steps never advance the state, and every tiling gives the same
     bits."""
