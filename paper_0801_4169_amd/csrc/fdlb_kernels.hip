@@ -12,10 +12,16 @@
 //   A6  store f_new (the other ping-pong half), then the moments of f_new give the
 //       pressure the next step's switching function reads, and the non-physical flag.
 //
-// Work decomposition: one workgroup per TX x TY tile, one thread per cell.  A thread keeps
-// its cell's 33 values in registers; neighbours come from an LDS copy of one or two
-// velocity planes of the tile plus a two-cell halo (double buffered, one barrier per
-// stage).  The halo of the next stage is fetched while the current one computes.
+// Work decomposition: one workgroup per TX x TY tile, one thread per cell.  Neighbours
+// come from an LDS copy of a pair of velocity planes of the tile plus a two-cell halo
+// (double buffered, one barrier per stage), and the planes of the next stages are in
+// flight while the current one computes.  Three bodies:
+//   step_body        (float32; float64 with FDLB_STREAM_EDGE=0 on edge tiles): the cell's
+//                    33 values in registers, moments recomputed from them;
+//   step_body_stream (float64): the moments stored by the previous step start the
+//                    equilibrium at once, the planes stream through the stages, and the
+//                    new moments are summed as the new values appear;
+//   step_body_dev    (deviation storage): f rebuilt in float64 from float32 deviations.
 // Workgroups are assigned to tiles so that each XCD (each L2) sweeps a contiguous band.
 //
 // Float64 mode evaluates every expression in one fixed order without contraction
@@ -488,6 +494,35 @@ __device__ __forceinline__ double load_P(const Inst &I, const double *__restrict
     return P[y * I.ppitch + x];
 }
 
+// As load_P, with the pressure of a cell inside the grid taken as n T of its stored
+// moments (the same product the step that stored them formed).
+__device__ __forceinline__ double load_P_m(const Inst &I, const double *__restrict__ M,
+                                           const double *__restrict__ PW, int x, int y, double t) {
+    const int nx = I.nx, ny = I.ny;
+    if ((unsigned)x >= (unsigned)nx) {
+        const int side = x < 0 ? 0 : 1;
+        const int yc = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+        int slot;
+        const int kind = side_kind(I, side, yc, t, slot);
+        if (kind == BC_DIRICHLET) return I.bcP[slot];
+        if (kind == BC_WALL) return PW[side * I.wlen + yc];
+        x = kind == BC_PERIODIC ? ((x % nx) + nx) % nx : (x < 0 ? 0 : nx - 1);
+    }
+    if ((unsigned)y >= (unsigned)ny) {
+        const int side = y < 0 ? 2 : 3;
+        const int xc = x < 0 ? 0 : (x >= nx ? nx - 1 : x);
+        int slot;
+        const int kind = side_kind(I, side, xc, t, slot);
+        if (kind == BC_DIRICHLET) return I.bcP[slot];
+        if (kind == BC_WALL) return PW[side * I.wlen + xc];
+        y = kind == BC_PERIODIC ? ((y % ny) + ny) % ny : (y < 0 ? 0 : ny - 1);
+    }
+    x = x < 0 ? 0 : (x >= nx ? nx - 1 : x);
+    y = y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+    const size_t c = (size_t)y * I.ppitch + x;
+    return M[c] * M[3 * (size_t)I.mplane + c];
+}
+
 // XCD-aware order: consecutive workgroup ids go round-robin over the 8 XCDs; give each XCD
 // a contiguous run of tiles so neighbouring tiles share an L2.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
@@ -498,6 +533,8 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 template <class S>
 constexpr bool stream_moments();
+template <class S>
+constexpr bool stream_edge();
 
 // Moments and pressure of the cell (from its final 33 values) and the pressure of the
 // mirror images next to reflecting sides.  Returns 1 if the cell's state is non-physical.
@@ -909,23 +946,26 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
     const double n = Mc[0], ux = Mc[I.mplane], uy = Mc[2 * I.mplane], T = Mc[3 * I.mplane];
     const double P0 = n * T;
     double Pxm, Pxp, Pym, Pyp;
+    // the neighbours' pressure: n T of their stored moments (no pressure plane)
     if constexpr (MODE == MODE_EDGE) {
-        const double *Pin = I.P[half], *PWin = I.PW[half];
-        Pxm = load_P(I, Pin, PWin, x - 1, y, tnow);
-        Pxp = load_P(I, Pin, PWin, x + 1, y, tnow);
-        Pym = load_P(I, Pin, PWin, x, y - 1, tnow);
-        Pyp = load_P(I, Pin, PWin, x, y + 1, tnow);
+        const double *Min = I.M[half], *PWin = I.PW[half];
+        Pxm = load_P_m(I, Min, PWin, x - 1, y, tnow);
+        Pxp = load_P_m(I, Min, PWin, x + 1, y, tnow);
+        Pym = load_P_m(I, Min, PWin, x, y - 1, tnow);
+        Pyp = load_P_m(I, Min, PWin, x, y + 1, tnow);
     } else {
-        const GLOBAL_AS double *Pin = (const GLOBAL_AS double *)I.P[half];
-        const GLOBAL_AS double *pc = Pin + (y * I.ppitch + x);
-        Pxm = pc[-1];
-        Pxp = pc[1];
+        const GLOBAL_AS double *Mn = (const GLOBAL_AS double *)I.M[half];
+        const GLOBAL_AS double *MT = Mn + 3 * (size_t)I.mplane;
+        const int c = y * I.ppitch + x;
+        Pxm = Mn[c - 1] * MT[c - 1];
+        Pxp = Mn[c + 1] * MT[c + 1];
         if constexpr (MODE == MODE_INTERIOR) {
-            Pym = pc[-I.ppitch];
-            Pyp = pc[I.ppitch];
+            Pym = Mn[c - I.ppitch] * MT[c - I.ppitch];
+            Pyp = Mn[c + I.ppitch] * MT[c + I.ppitch];
         } else {
-            Pym = Pin[(y == 0 ? ny - 1 : y - 1) * I.ppitch + x];
-            Pyp = Pin[(y == ny - 1 ? 0 : y + 1) * I.ppitch + x];
+            const int cm = (y == 0 ? ny - 1 : y - 1) * I.ppitch + x, cp = (y == ny - 1 ? 0 : y + 1) * I.ppitch + x;
+            Pym = Mn[cm] * MT[cm];
+            Pyp = Mn[cp] * MT[cp];
         }
     }
     const double ax = av_coeff(I.lam, Pxm, P0, Pxp, ux, I.dt, I.dx);
@@ -1014,7 +1054,8 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
         Mo[I.mplane] = ux2;
         Mo[2 * I.mplane] = uy2;
         Mo[3 * I.mplane] = T2;
-        ((GLOBAL_AS double *)I.P[1 - half])[y * I.ppitch + x] = P2;
+        // the pressure plane only for a register-resident edge body, which reads it
+        if constexpr (!stream_edge<S>()) ((GLOBAL_AS double *)I.P[1 - half])[y * I.ppitch + x] = P2;
     }
     const int bad = valid && nonphysical(I, n2, ux2, uy2, T2) ? 1 : 0;
     if (__syncthreads_or(bad) && tid == 0) *I.flag = 1;
