@@ -95,7 +95,9 @@ typedef struct {
 } fdlb_bc;
 
 typedef struct {
-    int32_t nx, ny;      /* cells; nx, ny >= 1, nx * ny <= 2^28, >= 2 across a wall */
+    int32_t nx, ny;      /* cells; nx, ny >= 1, nx * ny <= 2^28, >= 2 across a wall; in
+                            float64 also (nx rounded up to 32) * ny * 8 < 2^31 (a plane is
+                            addressed with 32-bit byte offsets) */
     double dx, dy;       /* cell sizes, > 0 */
     double dt, tau;      /* time step and BGK relaxation time, > 0 (Eq. bgk_eq) */
     double lambda;       /* artificial-viscosity amplitude, >= 0 (Eq. add4) */

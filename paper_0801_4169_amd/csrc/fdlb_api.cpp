@@ -78,6 +78,11 @@ bool finite_pos(double a) { return std::isfinite(a) && a > 0.0; }
 int validate(const fdlb_params &p) {
     if (p.nx < 1 || p.ny < 1) return 1;
     if ((int64_t)p.nx * p.ny > (int64_t)1 << 28) return 1;  // a plane stays below 2 GiB
+    // interior tiles address a plane with 32-bit byte offsets: the padded plane must fit
+    {
+        const int64_t esize = p.precision == FDLB_F64 ? 8 : 4;
+        if ((int64_t)round_up(p.nx, 32) * p.ny * esize > (int64_t)INT32_MAX) return 1;
+    }
     if (!finite_pos(p.dx) || !finite_pos(p.dy) || !finite_pos(p.dt) || !finite_pos(p.tau)) return 1;
     if (!std::isfinite(p.lambda) || p.lambda < 0.0) return 1;
     if (p.precision != FDLB_F64 && p.precision != FDLB_F32 && p.precision != FDLB_F32_DEV) return 1;

@@ -130,3 +130,14 @@ def test_failed_create_keeps_no_stale_message():
         B.fdlb_create(prm, 0, 0x1000, 1)
     assert e.value.status == B.FDLB_EINVAL
     assert B._lib.fdlb_last_error(None).decode() == ""
+
+
+def test_largest_planes():
+    """A plane holds at most 2^28 cells, and in float64 the row-padded plane (nx rounded up
+    to 32) must stay within the 32-bit byte offsets the interior tiles use."""
+    from paper_0801_4169_amd import _binding as B
+    ok = _sod_params(nx=16384, ny=16383)                      # 2 147 352 576 bytes per plane
+    assert B.fdlb_required_bytes(ok) > 0
+    assert B.fdlb_required_bytes(_sod_params(nx=16385, ny=16383)) == 0   # padded to 16416
+    assert B.fdlb_required_bytes(_sod_params(nx=16385, ny=16383, precision=B.FDLB_F32)) > 0
+    assert B.fdlb_required_bytes(_sod_params(nx=1 << 14, ny=(1 << 14) + 1, precision=B.FDLB_F32)) == 0
