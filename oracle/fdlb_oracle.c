@@ -15,7 +15,8 @@
  *     P = n T = sum (v - u)^2 f / 2, taken from f (equal to the f^eq sums by construction);
  *   - equilibrium: Sec. 2, Eqs. (feq_eq), (fk_eq1), (f0_eq), (kl_eq);
  *   - update: Sec. 3, Eq. (dis_eq1) with Eqs. (add3), (add4): lines I-IV per spatial
- *     direction alpha, summed over alpha = x, y, plus the BGK term once.
+ *     direction alpha, summed over alpha = x, y, plus the BGK term once; any of the four
+ *     lines may be left out (orc_params.lines), as Sec. 4 and Fig. 3 do.
  *
  * Readings where the paper is silent or garbled (each is listed in the design notes):
  *   R1  the bracket of Eq. (feq_eq) encloses all five groups (the printed one is unmatched);
