@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--mach", type=float, default=10.0, help="freestream Mach number of the inflow")
     ap.add_argument("--lam", type=float, default=20.0, help="artificial-viscosity amplitude lambda")
     ap.add_argument("--ensemble-steps", type=int, default=5000, help="steps of the 256-tube ensemble (0: skip)")
+    ap.add_argument("--accuracy-steps", type=int, default=2000,
+                    help="steps of the storages' accuracy check on the Mach-5 flow (0: skip)")
     ap.add_argument("--no-sensitivity", action="store_true",
                     help="skip the perturbed float64 run that measures the flow's own sensitivity")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps of the CPU baseline slice (0: skip)")
@@ -105,6 +107,25 @@ def timed_run(P, prob, fields, precision, steps, warmup, tile):
     del s
     torch.cuda.empty_cache()
     return dict(ms=ms, moments=m, flag=flag, k_ms=k_ms, k_cells=k_cells, tiling=tiling, copy_ms=copy_ms)
+
+
+def accuracy(P, fi, args):
+    """The three storages on the same grid and sides with freestream Mach 5 and lambda = 2
+    (a flow that does not amplify rounding: float64 with 1e-13 noise stays within 1e-11),
+    relative L1 of (rho, ux, uy, T) against float64 after args.accuracy_steps steps."""
+    import numpy as np
+    prob, fields, _ = fi.reflection_8192x2048(lam=2.0, nx=args.nx, ny=args.ny, mach=5.0)
+    n = args.accuracy_steps
+    ref = timed_run(P, prob, fields, "f64", n, 0, args.tile)["moments"]
+    rng = np.random.default_rng(1)
+    pert = (fields[0] * (1.0 + 1e-13 * rng.standard_normal(fields[0].shape)),) + tuple(fields[1:])
+    runs = {"f64_with_1e-13_noise": (pert, "f64"), "f32dev": (fields, "f32dev"), "f32": (fields, "f32")}
+    out = {"workload": prob["name"], "lambda": 2.0, "steps": n}
+    for name, (flds, pr) in runs.items():
+        r = timed_run(P, prob, flds, pr, n, 0, args.tile)
+        out[name] = {k: l1_rel(x, y) for k, x, y in zip(("rho", "ux", "uy", "T"), r["moments"], ref)}
+        out[name]["nonphysical"] = bool(r["flag"])
+    return out
 
 
 def l1_rel(a, b):
@@ -257,6 +278,9 @@ def main():
             a, b = o["moments"], res["f64"]["moments"]
             ent["l1_vs_f64_after_run"] = {k: l1_rel(x, y) for k, x, y in zip(("rho", "ux", "uy", "T"), a, b)}
         out[pr] = ent
+    if args.accuracy_steps > 0:
+        print("[bench] accuracy on a flow that is not chaotic (Mach 5, lambda 2)", file=sys.stderr, flush=True)
+        out["accuracy_mach5"] = accuracy(P, fi, args)
     if args.ensemble_steps > 0:
         print("[bench] ensemble", file=sys.stderr, flush=True)
         out["ensemble"] = ensemble(P, args.ensemble_steps)
