@@ -39,18 +39,19 @@ def _kind(b):
     return BC_NAMES[b] if isinstance(b, str) else int(b)
 
 
-def problem(nx, ny, dx, dt, tau, lam, bc, bc_state=None, dy=None, v=V_WT, name="", lower=None):
+def problem(nx, ny, dx, dt, tau, lam, bc, bc_state=None, dy=None, v=V_WT, name="", lower=None, lines=15):
     """Parameter dict of one problem.  ``bc`` is four kinds (names or codes), x-, x+, y-, y+.
     ``lower`` optionally gives each side a lower segment: None, or (kind, state, split,
     split_rate); ghost cells whose centre coordinate along the side is below
-    split + split_rate * t take that kind and state."""
+    split + split_rate * t take that kind and state.  ``lines``: the terms of Eq. (dis_eq1)
+    kept, bits 0..3 for lines I..IV (15: the full scheme)."""
     kinds = tuple(_kind(b) for b in bc)
     states = [(1.0, 0.0, 0.0, 1.0)] * 4 if bc_state is None else [tuple(map(float, s)) for s in bc_state]
     lo = tuple(None if g is None else (_kind(g[0]), tuple(map(float, g[1])), float(g[2]), float(g[3]))
                for g in (lower or (None,) * 4))
     return dict(name=name, nx=int(nx), ny=int(ny), dx=float(dx), dy=float(dx if dy is None else dy),
                 dt=float(dt), tau=float(tau), lam=float(lam), v=tuple(map(float, v)),
-                bc=kinds, bc_state=tuple(states), lower=lo)
+                bc=kinds, bc_state=tuple(states), lower=lo, lines=int(lines))
 
 
 def uniform_fields(nx, ny, state):
@@ -207,8 +208,7 @@ def fig3_tube(t=0.02, lines=15, ny=4):
     The domain [0, 1] (334 cells, jump at the middle) and the end time are not stated
     (reading: t = 0.02, before the shocks reach the ends)."""
     nx = 334
-    p = problem(nx, ny, 3e-3, 1e-5, 1e-5, 2.0, TUBE_BC, name=f"fig3_lines{lines}_{nx}x{ny}")
-    p["lines"] = int(lines)
+    p = problem(nx, ny, 3e-3, 1e-5, 1e-5, 2.0, TUBE_BC, name=f"fig3_lines{lines}_{nx}x{ny}", lines=lines)
     return p, riemann_fields(nx, ny, FIG3_L, FIG3_R), int(round(t / 1e-5))
 
 
