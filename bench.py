@@ -16,7 +16,10 @@ flow amplifies perturbations, so that is the floor any storage can reach); the 2
 ensemble in float64 and both float32 storages with per-instance L1 against float64; the
 roofline of the dominant kernel (interior tiles, timed alone with HIP events) against the
 MI355X HBM peak, HBM traffic from the committed counter summary when it matches the current
-kernel source, and the CPU oracle's rate on a bounded slice of the same grid.
+kernel source, and a plain copy of the same planes over the same tiles as the practical
+ceiling of the access pattern; the storages' accuracy on the same grid with a Mach-5 inflow,
+where float64 itself does not amplify rounding (`accuracy_mach5`); and the CPU oracle's
+rate on a bounded slice of the same grid.
 """
 import argparse
 import hashlib
