@@ -225,7 +225,9 @@ size_t fdlb_batch_required_bytes(int32_t k, const fdlb_params *p);
 fdlb_status fdlb_batch_create(int32_t k, const fdlb_params *p, void *stream, void *arena,
                               size_t arena_bytes, fdlb_ctx **out);
 /* Instance i (0 <= i < k).  set_state marks the batch as set once every instance has
- * been set at least once. */
+ * been set at least once.  The instances share one step clock and one non-physical flag,
+ * so once the batch has stepped, fdlb_batch_set_state returns FDLB_ESTATE (create a new
+ * batch to restart it). */
 fdlb_status fdlb_batch_set_state(fdlb_ctx *c, int32_t i, const double *rho, const double *ux,
                                  const double *uy, const double *T);
 fdlb_status fdlb_batch_get_moments(fdlb_ctx *c, int32_t i, double *rho, double *ux, double *uy,

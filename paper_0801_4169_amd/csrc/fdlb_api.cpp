@@ -258,6 +258,8 @@ struct fdlb_ctx {
     double *d_sums = nullptr;
     int half = 0;
     int64_t steps = 0;
+    bool stepped = false;  // some step was enqueued since creation (a batch shares one clock)
+    int device = 0;        // HIP device current at creation
     std::vector<char> is_set;
     bool state_set = false;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -290,6 +292,31 @@ fdlb_status create_fail(fdlb_ctx *c, hipError_t e, const char *what) {
         hipError_t e_ = (call);                                    \
         if (e_ != hipSuccess) return dev_fail((ctx), e_, #call);   \
     } while (0)
+
+// Two timing events, destroyed on every return path.
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t create() {
+        hipError_t e = hipEventCreate(&e0);
+        return e != hipSuccess ? e : hipEventCreate(&e1);
+    }
+    ~EventPair() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+// Trial launches (kernel timing, copy ceiling, autotuning) step from the current half into
+// the spare one without taking the step, but their kernels still raise the sticky
+// non-physical flag from values the state never holds.  The keeper reads the flag before
+// the trials and writes that value back after them, on every return path (the calls using
+// it synchronise the stream anyway).
+struct FlagKeeper {
+    fdlb_ctx *c = nullptr;
+    int32_t saved = 0;
+    hipError_t save(fdlb_ctx *ctx);
+    ~FlagKeeper();
+};
 
 void release(fdlb_ctx *c) {
     if (!c) return;
@@ -353,7 +380,13 @@ fdlb_status set_tiles(fdlb_ctx *c, int shape, int group) {
         c->d_tiles[kd] = nullptr;
         c->ntiles[kd] = (int)tiles[kd].size();
         if (tiles[kd].empty()) continue;
-        if (hipMalloc(&c->d_tiles[kd], sizeof(Tile) * tiles[kd].size()) != hipSuccess) return FDLB_ENOMEM;
+        const hipError_t e = hipMalloc(&c->d_tiles[kd], sizeof(Tile) * tiles[kd].size());
+        if (e != hipSuccess) {
+            c->d_tiles[kd] = nullptr;
+            c->ntiles[kd] = 0;
+            c->err = std::string("hipMalloc(tile table): ") + hipGetErrorString(e);
+            return e == hipErrorOutOfMemory ? FDLB_ENOMEM : FDLB_EDEVICE;
+        }
         HIPCHK(c, hipMemcpyAsync(c->d_tiles[kd], tiles[kd].data(), sizeof(Tile) * tiles[kd].size(),
                                  hipMemcpyHostToDevice, c->stream));
     }
@@ -390,6 +423,7 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
     c->group = default_group(c->prec);
 
     hipError_t e;
+    if ((e = hipGetDevice(&c->device)) != hipSuccess) return create_fail(c, e, "hipGetDevice");
     if ((e = hipMalloc(&c->d_flag, sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&c->d_clock, sizeof(int64_t))) != hipSuccess)
         return create_fail(c, e, "hipMalloc");
@@ -471,6 +505,20 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
     g_create_err.clear();
     *out = c;
     return FDLB_OK;
+}
+
+hipError_t FlagKeeper::save(fdlb_ctx *ctx) {
+    hipError_t e = hipMemcpyAsync(&saved, ctx->d_flag, sizeof(saved), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) c = ctx;
+    return e;
+}
+
+FlagKeeper::~FlagKeeper() {
+    if (!c) return;
+    // `saved` lives in this object: wait for the copy before it goes away
+    if (hipMemcpyAsync(c->d_flag, &saved, sizeof(saved), hipMemcpyHostToDevice, c->stream) == hipSuccess)
+        (void)hipStreamSynchronize(c->stream);
 }
 
 fdlb_status check_flag(fdlb_ctx *c) {
@@ -618,12 +666,16 @@ fdlb_status fdlb_set_state_device(fdlb_ctx *c, const double *fields) {
 fdlb_status fdlb_batch_set_state(fdlb_ctx *c, int32_t i, const double *rho, const double *ux, const double *uy,
                                  const double *T) {
     if (!c || i < 0 || i >= c->k) return FDLB_EINVAL;
+    // the instances share one step clock and one non-physical flag: setting one instance
+    // after the batch has stepped would restart the clock and clear the flag of all others
+    if (c->k > 1 && c->stepped) return FDLB_ESTATE;
     return set_instance_host(c, i, rho, ux, uy, T);
 }
 
 fdlb_status fdlb_step(fdlb_ctx *c, int64_t nsteps) {
     if (!c || nsteps < 0) return FDLB_EINVAL;
     if (!c->state_set) return FDLB_ESTATE;
+    if (nsteps > 0) c->stepped = true;
     int64_t left = nsteps;
     while (left >= kGraphSteps) {
         fdlb_status s = ensure_graph(c, c->half);
@@ -781,12 +833,13 @@ int64_t fdlb_tile_cells(const fdlb_ctx *c, int32_t kind) {
 fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float *ms_per_launch) {
     if (!c || !ms_per_launch || launches < 1 || kind < -1 || kind >= fdlb::kNumTileKinds) return FDLB_EINVAL;
     if (!c->state_set) return FDLB_ESTATE;
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    FlagKeeper keep;
+    HIPCHK(c, keep.save(c));
+    EventPair ev;
+    HIPCHK(c, ev.create());
     const int h = c->half;
     for (int w = 0; w < 2 + launches; ++w) {
-        if (w == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
+        if (w == 2) HIPCHK(c, hipEventRecord(ev.e0, c->stream));
         for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
             if (c->ntiles[kd] > 0 && (kind < 0 || kd == kind))
                 HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], h,
@@ -794,12 +847,10 @@ fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float 
         if (kind < 0 && c->wall_len > 0)
             HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - h, c->stream));
     }
-    HIPCHK(c, hipEventRecord(e1, c->stream));
-    HIPCHK(c, hipEventSynchronize(e1));
+    HIPCHK(c, hipEventRecord(ev.e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(ev.e1));
     float ms = 0.0f;
-    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIPCHK(c, hipEventElapsedTime(&ms, ev.e0, ev.e1));
     *ms_per_launch = ms / (float)launches;
     return FDLB_OK;
 }
@@ -808,20 +859,17 @@ fdlb_status fdlb_copy_ceiling(fdlb_ctx *c, int32_t launches, float *ms_per_launc
     if (!c || !ms_per_launch || launches < 1) return FDLB_EINVAL;
     if (!c->state_set) return FDLB_ESTATE;
     if (c->ntiles[0] == 0) return FDLB_EINVAL;
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    EventPair ev;
+    HIPCHK(c, ev.create());
     const int h = c->half;
     for (int w = 0; w < 2 + launches; ++w) {
-        if (w == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
+        if (w == 2) HIPCHK(c, hipEventRecord(ev.e0, c->stream));
         HIPCHK(c, fdlb::launch_plane_copy(c->prec, c->shape, c->d_insts, c->d_tiles[0], c->ntiles[0], h, c->stream));
     }
-    HIPCHK(c, hipEventRecord(e1, c->stream));
-    HIPCHK(c, hipEventSynchronize(e1));
+    HIPCHK(c, hipEventRecord(ev.e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(ev.e1));
     float ms = 0.0f;
-    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIPCHK(c, hipEventElapsedTime(&ms, ev.e0, ev.e1));
     *ms_per_launch = ms / (float)launches;
     return FDLB_OK;
 }
@@ -842,9 +890,10 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
     if (sh.empty())
         for (int s = 0; s < fdlb::kNumTileShapes; ++s) sh.push_back(s);
     if (gr.empty()) gr = {1, 4, 8, 16, 32};
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    FlagKeeper keep;
+    HIPCHK(c, keep.save(c));
+    EventPair ev;
+    HIPCHK(c, ev.create());
     float best = -1.0f;
     int best_s = c->shape, best_g = c->group;
     const int h = c->half;
@@ -855,7 +904,7 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
             // trial steps read the current half and write the other one without swapping:
             // the state is left exactly as it was
             for (int w = 0; w < 2 + trial_steps; ++w) {
-                if (w == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
+                if (w == 2) HIPCHK(c, hipEventRecord(ev.e0, c->stream));
                 for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
                     if (c->ntiles[kd] > 0)
                         HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd],
@@ -863,10 +912,10 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
                 if (c->wall_len > 0)
                     HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - h, c->stream));
             }
-            HIPCHK(c, hipEventRecord(e1, c->stream));
-            HIPCHK(c, hipEventSynchronize(e1));
+            HIPCHK(c, hipEventRecord(ev.e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(ev.e1));
             float ms = 0.0f;
-            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            HIPCHK(c, hipEventElapsedTime(&ms, ev.e0, ev.e1));
             ms /= (float)trial_steps;
             if (best < 0.0f || ms < best) {
                 best = ms;
@@ -874,8 +923,6 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
                 best_g = g;
             }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (best_ms) *best_ms = best;
     return set_tiles(c, best_s, best_g);
 }
