@@ -165,6 +165,17 @@ fdlb_status fdlb_set_f(fdlb_ctx *c, const void *host, size_t bytes);
  * non-physical flag (0/1).  Deterministic (fixed reduction order).  Syncs. */
 fdlb_status fdlb_diag(fdlb_ctx *c, double sums[4], int32_t *nonphys);
 
+/* As fdlb_diag, for callers that cannot allocate device memory (code under HIP graph
+ * capture of their own work, tight serving loops, harnesses that forbid hipMalloc): the
+ * reduction's partial totals and final sums go to a fixed scratch array compiled into the
+ * library (2 MiB per GPU, held until the process ends) instead of the context's blocks.
+ * The call itself allocates nothing.  Limit: the context's grids together may hold at
+ * most 2^24 cells (2^16 blocks of 256); larger ones get FDLB_EINVAL with the sizes in
+ * fdlb_last_error(c).  Same totals, bit for bit, as fdlb_diag.  All contexts on one GPU
+ * share that GPU's scratch: calls that overlap in time on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller.  Syncs the context's stream. */
+fdlb_status fdlb_diag_noalloc(fdlb_ctx *c, double sums[4], int32_t *nonphys);
+
 /* Steps taken since the last state was set. */
 int64_t fdlb_steps_done(const fdlb_ctx *c);
 

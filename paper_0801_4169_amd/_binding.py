@@ -77,6 +77,7 @@ _sigs = {
     "fdlb_get_f": (ctypes.c_int, [_CTX, ctypes.c_void_p, ctypes.c_size_t]),
     "fdlb_set_f": (ctypes.c_int, [_CTX, ctypes.c_void_p, ctypes.c_size_t]),
     "fdlb_diag": (ctypes.c_int, [_CTX, _DP, ctypes.POINTER(ctypes.c_int32)]),
+    "fdlb_diag_noalloc": (ctypes.c_int, [_CTX, _DP, ctypes.POINTER(ctypes.c_int32)]),
     "fdlb_steps_done": (ctypes.c_int64, [_CTX]),
     "fdlb_set_clock": (ctypes.c_int, [_CTX, ctypes.c_int64]),
     "fdlb_destroy": (None, [_CTX]),
@@ -236,6 +237,14 @@ def fdlb_diag(ctx):
     sums = np.zeros(4)
     flag = ctypes.c_int32(0)
     _check(_lib.fdlb_diag(ctx, _ptr(sums), ctypes.byref(flag)), ctx)
+    return sums, bool(flag.value)
+
+
+def fdlb_diag_noalloc(ctx):
+    """fdlb_diag through the library's fixed scratch (the call allocates no device memory)."""
+    sums = np.zeros(4)
+    flag = ctypes.c_int32(0)
+    _check(_lib.fdlb_diag_noalloc(ctx, _ptr(sums), ctypes.byref(flag)), ctx)
     return sums, bool(flag.value)
 
 

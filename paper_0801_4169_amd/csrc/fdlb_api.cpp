@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -787,6 +788,61 @@ fdlb_status fdlb_diag(fdlb_ctx *c, double sums[4], int32_t *nonphys) {
     }
     HIPCHK(c, fdlb::launch_diag_final(c->d_partials, c->nparts, c->d_sums, c->stream));
     HIPCHK(c, hipMemcpyAsync(sums, c->d_sums, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    fdlb_status s = check_flag(c);
+    if (nonphys) *nonphys = s == FDLB_ENONPHYS ? 1 : 0;
+    return s == FDLB_ENONPHYS ? FDLB_OK : s;
+}
+
+}  // extern "C"
+
+namespace {
+// Per-device address of the allocation-free diagnostics scratch, resolved once per device
+// with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+hipError_t scratch_for(int device, double **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        double *ptr = nullptr;
+        e = fdlb::diag_scratch_address(&ptr);
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        g_scratch[device] = ptr;
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+fdlb_status fdlb_diag_noalloc(fdlb_ctx *c, double sums[4], int32_t *nonphys) {
+    if (!c || !sums) return FDLB_EINVAL;
+    if (c->nparts > fdlb::kDiagScratchParts) {
+        c->err = "fdlb_diag_noalloc: the grid needs " + std::to_string(c->nparts) +
+                 " partial blocks of 256 cells; the fixed scratch holds " +
+                 std::to_string(fdlb::kDiagScratchParts);
+        return FDLB_EINVAL;
+    }
+    if (!c->state_set) return FDLB_ESTATE;
+    double *scr = nullptr;
+    HIPCHK(c, scratch_for(c->device, &scr));
+    double *dsums = scr + 4 * (size_t)fdlb::kDiagScratchParts;
+    int off = 0;
+    for (int i = 0; i < c->k; ++i) {
+        const fdlb_params &p = c->params[i];
+        HIPCHK(c, fdlb::launch_diag(c->prec, c->d_insts, i, p.nx, p.ny, c->half, scr, off, c->stream));
+        off += fdlb::diag_blocks(p.nx, p.ny);
+    }
+    HIPCHK(c, fdlb::launch_diag_final(scr, c->nparts, dsums, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sums, dsums, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     fdlb_status s = check_flag(c);
     if (nonphys) *nonphys = s == FDLB_ENONPHYS ? 1 : 0;
     return s == FDLB_ENONPHYS ? FDLB_OK : s;

@@ -90,6 +90,11 @@ hipError_t launch_moments(int prec, const Inst *insts, int inst, int nx, int ny,
 hipError_t launch_diag(int prec, const Inst *insts, int inst, int nx, int ny, int half, double *partials,
                        int npart_offset, hipStream_t s);
 hipError_t launch_diag_final(const double *partials, int nparts, double *sums, hipStream_t s);
+// Partial blocks (of 256 cells) the fixed scratch of the allocation-free diagnostics holds:
+// 2^16 blocks, 2^24 cells over all instances of a context (2 MiB of float64 partials).
+constexpr int kDiagScratchParts = 1 << 16;
+// Device address of that scratch on the current device (hipGetSymbolAddress).
+hipError_t diag_scratch_address(double **ptr);
 hipError_t launch_tick(int64_t *clock, hipStream_t s);
 // Float64 edge tiles run the streaming body (FDLB_STREAM_EDGE=0: the register-resident
 // body, which writes the wall-image pressures itself).

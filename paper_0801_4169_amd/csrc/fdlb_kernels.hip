@@ -1976,6 +1976,17 @@ hipError_t launch_tick(int64_t *clock, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Fixed scratch of the allocation-free diagnostics (fdlb_diag_noalloc): the per-block
+// partial totals of launch_diag, then the four final sums.  Every block writes its own
+// four partials and the final kernel writes the sums, so nothing needs clearing between
+// calls.  Each GPU holds its own copy for the life of the process; host code must use
+// the address diag_scratch_address returns, never the symbol itself.
+static __device__ __align__(256) double scratch[4 * kDiagScratchParts + 4];
+
+hipError_t diag_scratch_address(double **ptr) {
+    return hipGetSymbolAddress(reinterpret_cast<void **>(ptr), HIP_SYMBOL(scratch));
+}
+
 hipError_t launch_diag_final(const double *partials, int nparts, double *sums, hipStream_t s) {
     hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kDiagBlock), 0, s, partials, nparts, sums);
     return hipGetLastError();
