@@ -142,16 +142,47 @@ def moving_shock_state(pre_rho, pre_T, mach, direction_deg, gamma=GAMMA_WT):
     return (rho2, speed * math.cos(d), speed * math.sin(d), p2 / rho2)
 
 
-def reflection_fields(nx, ny, dx, pre, post, beta_deg, dy=None):
+def blend_states(pre, post, s):
+    """Fields that pass from ``pre`` (s = 0) to ``post`` (s = 1): the conserved densities
+    n, n u, n (|u|^2 / 2 + T) are mixed linearly with weight s (an array), then turned back
+    into (n, ux, uy, T).  Every blend of two physical states is physical."""
+    s = np.asarray(s, dtype=np.float64)
+    r0, u0, v0, T0 = map(float, pre)
+    r1, u1, v1, T1 = map(float, post)
+    n = r0 * (1 - s) + r1 * s
+    jx = r0 * u0 * (1 - s) + r1 * u1 * s
+    jy = r0 * v0 * (1 - s) + r1 * v1 * s
+    E = r0 * (0.5 * (u0 * u0 + v0 * v0) + T0) * (1 - s) + r1 * (0.5 * (u1 * u1 + v1 * v1) + T1) * s
+    ux, uy = jx / n, jy / n
+    T = E / n - 0.5 * (ux * ux + uy * uy)
+    return tuple(np.ascontiguousarray(a) for a in (n, ux, uy, T))
+
+
+def shock_profile(dist, width):
+    """Weight of the post-shock state at signed distance ``dist`` (cells, positive on the
+    post-shock side) from a shock line: a step for width 0, else the smooth profile
+    (1 + tanh(dist / width)) / 2."""
+    if width <= 0:
+        return (np.asarray(dist) >= 0).astype(np.float64)
+    return 0.5 * (1.0 + np.tanh(np.asarray(dist) / float(width)))
+
+
+def reflection_fields(nx, ny, dx, pre, post, beta_deg, dy=None, width=0.0):
     """Initial field of the steady regular reflection: post-shock above the incident shock
-    line y = Ly - x tan(beta) drawn from the top-left corner, pre-shock below."""
+    line y = Ly - x tan(beta) drawn from the top-left corner, pre-shock below.  ``width``
+    (cells) smooths the line into a tanh profile of the conserved densities across it
+    (0: a sharp staircase of cells)."""
     dy = dx if dy is None else dy
     Ly = ny * dy
     x = (np.arange(nx) + 0.5) * dx
     y = (np.arange(ny) + 0.5) * dy
     X, Y = np.meshgrid(x, y)
-    above = Y >= Ly - X * math.tan(math.radians(beta_deg))
-    return tuple(np.ascontiguousarray(np.where(above, float(b), float(a))) for a, b in zip(pre, post))
+    if width <= 0:
+        above = Y >= Ly - X * math.tan(math.radians(beta_deg))
+        return tuple(np.ascontiguousarray(np.where(above, float(b), float(a))) for a, b in zip(pre, post))
+    b = math.radians(beta_deg)
+    dist = (Y - (Ly - X * math.tan(b))) * math.cos(b) / dy  # normal distance in cells
+    return blend_states(pre, post, shock_profile(dist, width))
 
 
 # --------------------------------------------------------------------------------------
@@ -228,29 +259,69 @@ def regular_reflection(nx, ny, dx, dt, tau, lam, pre, post, beta_deg, name):
     return p, reflection_fields(nx, ny, dx, pre, post, beta_deg)
 
 
-def reflection_1024x256(lam=2.0, mach=None):
+def reflection_1024x256(lam=20.0, mach=10.0, mach_n=None, width=0.0, tau=1e-5):
     """Shock incident at 29 degrees on a reflecting wall, 1024 x 256 cells, dx = 1e-3,
-    dt = 5e-6, tau = 1e-5, 40000 steps.  mach=None: the shock's normal Mach number is 10
-    (pre-shock T = 0.5, so u = 10 / sin 29deg); mach=M: freestream (1, M, 0, 0.5)."""
-    if mach is None:
-        post, pre = oblique_shock_state((1.0, 1.0, 0.0, 0.5), mach_n=10.0, beta_deg=29.0)
-        tag = "mn10"
+    dt = 5e-6, tau = 1e-5, 40000 steps.  ``mach``: freestream (1, mach, 0, 0.5), the paper's
+    way of naming a reflection's Mach number (Sec. 5.2.1: "Mach number 20" with a printed
+    post-shock state that is the freestream Mach 20 one); ``mach_n`` instead fixes the
+    shock-normal Mach number (pre-shock T = 0.5, u = mach_n c / sin 29deg).  ``width``:
+    smoothing of the initial shock line in cells (see reflection_fields)."""
+    if mach_n is not None:
+        post, pre = oblique_shock_state((1.0, 1.0, 0.0, 0.5), mach_n=float(mach_n), beta_deg=29.0)
+        tag = f"mn{mach_n:g}"
     else:
         post, pre = oblique_shock_state((1.0, float(mach), 0.0, 0.5), beta_deg=29.0)
         tag = f"m{mach:g}"
-    p, f = regular_reflection(1024, 256, 1e-3, 5e-6, 1e-5, lam, pre, post, 29.0,
-                              f"reflection_{tag}_29deg_1024x256")
-    return p, f, 40000
+    p = regular_reflection_problem(1024, 256, 1e-3, 5e-6, tau, lam, pre, post, f"reflection_{tag}_29deg_1024x256")
+    return p, reflection_fields(1024, 256, 1e-3, pre, post, 29.0, width=width), 40000
 
 
-def reflection_8192x2048(lam=2.0, nx=8192, ny=2048, mach=20.0):
+def reflection_8192x2048(lam=2.0, nx=8192, ny=2048, mach=20.0, tau=2e-6, width=0.0):
     """Freestream (1, mach, 0, 0.5) with a 30-degree incident shock (Sec. 5.2.1 has
-    mach = 20), 2.048 x 0.512 domain, 8192 x 2048 cells, dx = 2.5e-4, dt = 1e-6,
-    tau = 2e-6, 10000 steps."""
+    mach = 20), 2.048 x 0.512 domain, 8192 x 2048 cells, dx = 2.5e-4, dt = 1e-6, tau as
+    given (2e-6 by default), 10000 steps; ``width`` smooths the initial shock line."""
     post, pre = oblique_shock_state((1.0, float(mach), 0.0, 0.5), beta_deg=30.0)
-    p, f = regular_reflection(nx, ny, 2.5e-4, 1e-6, 2e-6, lam, pre, post, 30.0,
-                              f"reflection_m{mach:g}_30deg_{nx}x{ny}")
-    return p, f, 10000
+    p = regular_reflection_problem(nx, ny, 2.5e-4, 1e-6, tau, lam, pre, post, f"reflection_m{mach:g}_30deg_{nx}x{ny}")
+    return p, reflection_fields(nx, ny, 2.5e-4, pre, post, 30.0, width=width), 10000
+
+
+def regular_reflection_problem(nx, ny, dx, dt, tau, lam, pre, post, name):
+    p, _ = regular_reflection(nx, ny, dx, dt, tau, lam, pre, post, 30.0, name)
+    return p
+
+
+# The reflections as this build runs them (readings of Sec. 5.2.1; the sharp staircase start
+# and the shock-normal reading of "Mach 10" turn non-physical with the printed scheme):
+#   - the initial incident shock is smoothed over two cells (tanh of the conserved densities);
+#   - the paper's own grid keeps its printed dt = tau = 1e-5 with lambda = 20 (the paper's
+#     value for its strongest tube, Colella's);
+#   - the 8192 x 2048 Mach-20 grid takes tau = dt (as every strong-shock run of the paper
+#     does) and lambda = 40: with tau = 2 dt, or lambda <= 30, it turns non-physical within
+#     2000-4000 steps;
+#   - "Mach 10 at 29 degrees" is freestream Mach 10, the paper's convention.
+SMOOTH_WIDTH = 2.0
+
+
+def paper_reflection(lam=20.0, width=SMOOTH_WIDTH):
+    """The steady regular reflection of Sec. 5.2.1 at the paper's parameters: 300 x 100
+    cells of 3e-3, inflow (1, 20, 0, 0.5) on the left, the printed post-shock state on the
+    top, reflecting wall at the bottom, outflow on the right, dt = tau = 1e-5 (the value of
+    all the paper's strong-shock runs), 20000 steps to t = 0.2."""
+    p, _ = regular_reflection(300, 100, 3e-3, 1e-5, 1e-5, lam, REFL_PRE, REFL_POST_PRINTED, 30.0,
+                              f"paper_reflection_m20_300x100_lam{lam:g}")
+    return p, reflection_fields(300, 100, 3e-3, REFL_PRE, REFL_POST_PRINTED, 30.0, width=width), 20000
+
+
+def cfg3_reflection():
+    """The 1024 x 256 reflection as run: freestream Mach 10 at 29 degrees, lambda = 20,
+    tau = 1e-5 as specified, smoothed start, 40000 steps."""
+    return reflection_1024x256(lam=20.0, mach=10.0, width=SMOOTH_WIDTH)
+
+
+def cfg5_reflection(nx=8192, ny=2048):
+    """The 8192 x 2048 reflection as run: the paper's Mach-20 inflow and 30-degree shock,
+    tau = dt = 1e-6, lambda = 40, smoothed start, 10000 steps."""
+    return reflection_8192x2048(lam=40.0, nx=nx, ny=ny, mach=20.0, tau=1e-6, width=SMOOTH_WIDTH)
 
 
 def ensemble_draws(count=256, seed=0, log_rp_max=2.0):
@@ -290,7 +361,7 @@ def ensemble_tubes(count=256, seed=0, ny=4, log_rp_max=2.0, tau_factor=1.0, lam=
     return probs, 5000
 
 
-def double_mach(nx=500, ny=200, dx=1e-3, dt=1e-5, tau=1e-5, lam=2.0, mach=20.0):
+def double_mach(nx=500, ny=200, dx=1e-3, dt=1e-5, tau=1e-5, lam=2.0, mach=20.0, width=0.0):
     """Double Mach reflection (Sec. 5.2.2): a shock at 60 degrees to the x axis moving right
     at normal speed 20 into (2, 0, 0, 0.5); post-shock above the line
     y = sqrt(3) (x - 80 dx) - 40 t at t = 0, pre-shock below.  Sides: post-shock Dirichlet
@@ -300,7 +371,8 @@ def double_mach(nx=500, ny=200, dx=1e-3, dt=1e-5, tau=1e-5, lam=2.0, mach=20.0):
     cells (dx = 1e-3) for 750 steps and states no dt, tau or lambda: dt = tau = 1e-5 as in
     its other strong-shock runs, lambda as chosen.  ``mach`` != 20 runs the same geometry
     with a weaker shock: normal speed ``mach`` (the line moves as sqrt(3)(x - x0) - 2 mach t)
-    and the Rankine-Hugoniot post-shock state at gamma = 2."""
+    and the Rankine-Hugoniot post-shock state at gamma = 2.  ``width`` (cells) smooths the
+    initial shock line into a tanh profile of the conserved densities (0: sharp)."""
     pre = DMR_PRE
     post = DMR_POST_PRINTED if mach == 20.0 else moving_shock_state(pre[0], pre[3], mach, -30.0)
     x0 = 80 * dx
@@ -309,8 +381,12 @@ def double_mach(nx=500, ny=200, dx=1e-3, dt=1e-5, tau=1e-5, lam=2.0, mach=20.0):
     x = (np.arange(nx) + 0.5) * dx
     y = (np.arange(ny) + 0.5) * dx
     X, Y = np.meshgrid(x, y)
-    above = Y >= r3 * (X - x0)
-    fields = tuple(np.ascontiguousarray(np.where(above, float(b), float(a))) for a, b in zip(pre, post))
+    if width > 0:
+        dist = (Y - r3 * (X - x0)) * 0.5 / dx  # normal distance to the 60-degree line, cells
+        fields = blend_states(pre, post, shock_profile(dist, width))
+    else:
+        above = Y >= r3 * (X - x0)
+        fields = tuple(np.ascontiguousarray(np.where(above, float(b), float(a))) for a, b in zip(pre, post))
     bc = ("dirichlet", "outflow", "wall", "dirichlet")
     states = (post, post, post, pre)
     lower = (None, None, ("dirichlet", post, x0, 0.0), ("dirichlet", post, x0 + Ly / r3, 2.0 * mach / r3))

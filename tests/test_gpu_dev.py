@@ -165,7 +165,7 @@ def test_dev_much_closer_than_f32_on_mach5_reflection(P):
     """Mach-5 reflection (1024 x 256), 200 steps: both storages against the oracle; the
     deviation storage is at least 100 times closer in L1."""
     say("dev vs f32 reflection mach 5, 200 steps")
-    prob, flds, _ = fi.reflection_1024x256(mach=5.0)
+    prob, flds, _ = fi.reflection_1024x256(lam=2.0, mach=5.0)
     md, _ = run(P, prob, flds, 200)
     m32, _ = run(P, prob, flds, 200, precision="f32")
     ref, _ = oracle.run_state(prob, flds, 200, nthreads=NTHR)

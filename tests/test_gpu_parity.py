@@ -194,7 +194,7 @@ def test_reflection_1024x256_freestream_mach5_bitwise(P):
     """The 29-degree reflection at freestream Mach 5 (a reading that stays physical for the
     full 40000 steps), 40 steps on the full grid."""
     say("reflection 1024x256 mach 5, 40 steps")
-    prob, flds, _ = fi.reflection_1024x256(mach=5.0)
+    prob, flds, _ = fi.reflection_1024x256(lam=2.0, mach=5.0)
     f_gpu, _ = gpu_run(P, prob, flds, 40)
     f_ref, bad = oracle.run_f(prob, oracle.init_state(prob, flds), 40, nthreads=NTHR)
     assert bad == -1
@@ -206,7 +206,7 @@ def test_reflection_1024x256_normal_mach10_bitwise_while_finite(P):
     the oracle as in the GPU path (T < 0 below the incident shock); the two agree bit for bit
     while every value is finite."""
     say("reflection 1024x256 normal mach 10, 3 steps")
-    prob, flds, _ = fi.reflection_1024x256()
+    prob, flds, _ = fi.reflection_1024x256(lam=2.0, mach_n=10.0)
     f_gpu, _ = gpu_run(P, prob, flds, 3)
     f_ref, bad = oracle.run_f(prob, oracle.init_state(prob, flds), 3, nthreads=NTHR)
     assert bad == 2
