@@ -109,12 +109,19 @@ typedef struct {
                             difference, Lax-Wendroff dissipation, dispersion, artificial
                             viscosity); 0 or 15 = the full scheme.  Sec. 4 and Fig. 3 study
                             the scheme with lines left out; the BGK term is always kept. */
-    int32_t pad_;
+    int32_t tblock;      /* time steps per pass over memory: 0 or 1 = one; 2 (FDLB_F64 only)
+                            = tiles whose 16 x 8 cells and four cells around them lie inside
+                            the grid take two steps per launch, keeping the intermediate step
+                            in on-chip memory (the stencil reaches two cells per step); the
+                            other tiles take single steps through a third buffer.  The
+                            values are those of single steps bit for bit; the tile shape is
+                            16 x 8 (shape id 8); the context borrows three buffers instead of
+                            two. */
 } fdlb_params;
 
-/* Bytes of device memory a context for these parameters borrows (both ping-pong halves:
- * 33 distribution planes, the pressure plane and the wall-pressure rows).  0 if the
- * parameters are invalid. */
+/* Bytes of device memory a context for these parameters borrows (both ping-pong halves,
+ * and the intermediate buffer when tblock = 2: 33 distribution planes, the moment and
+ * pressure planes and the wall-pressure rows each).  0 if the parameters are invalid. */
 size_t fdlb_required_bytes(const fdlb_params *p);
 
 /* Creates a context.  `arena` is a device pointer to at least fdlb_required_bytes(p)
@@ -212,9 +219,11 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
                           const int32_t *groups, int32_t ngroups, float *best_ms);
 
 /* Measurement: the step is one launch per tile kind (0 interior tiles, 1 tiles spanning a
- * periodic height of one tile, 2 tiles touching a side).  fdlb_tile_cells gives the grid
+ * periodic height of one tile, 2 tiles touching a side; with tblock = 2 also 3, the
+ * two-step tiles, whose launch takes two steps).  fdlb_tile_cells gives the grid
  * cells a kind covers; fdlb_time_kernel times `launches` launches of one kind (-1: the
- * whole step) with HIP events on the context's stream, without advancing the state (like
+ * whole step, `launches` steps; with tblock = 2 they run as two-step passes and the time
+ * is per step) with HIP events on the context's stream, without advancing the state (like
  * the autotuner's trial steps).  Syncs. */
 int64_t fdlb_tile_cells(const fdlb_ctx *c, int32_t kind);
 fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float *ms_per_launch);

@@ -56,6 +56,10 @@ size_t plane_pad_bytes() {
     return kPlanePad;
 }
 
+// Buffer slots a context borrows: the two ping-pong halves, and with two steps per pass the
+// intermediate step's buffer.
+int nslots(const fdlb_params &p) { return p.tblock == 2 ? 3 : 2; }
+
 Layout layout_of(const fdlb_params &p) {
     Layout L{};
     L.esize = p.precision == FDLB_F64 ? 8 : 4;
@@ -69,7 +73,7 @@ Layout layout_of(const fdlb_params &p) {
     L.p_bytes = align_up((size_t)p.ny * L.ppitch * 8, kAlign);
     L.m_bytes = align_up((size_t)4 * L.mplane * 8, kAlign);
     L.w_bytes = align_up((size_t)4 * L.wlen * 8, kAlign);
-    L.total = 2 * (L.f_bytes + L.p_bytes + L.m_bytes + L.w_bytes);
+    L.total = (size_t)nslots(p) * (L.f_bytes + L.p_bytes + L.m_bytes + L.w_bytes);
     return L;
 }
 
@@ -89,6 +93,8 @@ int validate(const fdlb_params &p) {
     if (p.precision != FDLB_F64 && p.precision != FDLB_F32 && p.precision != FDLB_F32_DEV) return 1;
     if (p.tile < 0 || p.tile > fdlb::kNumTileShapes) return 1;
     if (p.lines < 0 || p.lines > 15) return 1;
+    if (p.tblock < 0 || p.tblock > 2) return 1;
+    if (p.tblock == 2 && p.precision != FDLB_F64) return 1;  // two-step passes: float64 only
     double vmax = 0.0;
     for (int k = 0; k < 4; ++k) {
         if (!finite_pos(p.v[k])) return 1;
@@ -151,6 +157,7 @@ bool default_fork() {
 // and the deviation layout; 64 x 4 when the grid is four cells high (one tile spans a
 // tube's periodic height).
 int default_shape(const fdlb_params &p) {
+    if (p.tblock == 2) return fdlb::kTwoStepShape;  // the two-step kernel's tiles set the grid
     if (p.tile > 0) return p.tile - 1;
     if (p.ny == 4) return 1;
     return p.precision == FDLB_F64 ? 3 : 0;
@@ -248,8 +255,9 @@ struct fdlb_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool fork = true;
     Inst *d_insts = nullptr;
-    Tile *d_tiles[fdlb::kNumTileKinds] = {nullptr, nullptr, nullptr};
-    int ntiles[fdlb::kNumTileKinds] = {0, 0, 0};
+    Tile *d_tiles[fdlb::kNumTileKinds] = {nullptr, nullptr, nullptr, nullptr};
+    int ntiles[fdlb::kNumTileKinds] = {0, 0, 0, 0};
+    int tblock = 1;  // steps per pass of the two-step tiles (2) or single steps only (1)
     int32_t *d_flag = nullptr;
     int64_t *d_clock = nullptr;  // steps since the state was set (moving side segments)
     bool ticks = false;          // some instance has a moving side segment
@@ -319,6 +327,17 @@ struct FlagKeeper {
     ~FlagKeeper();
 };
 
+// Kind of the tile at (x0, y0): with two steps per pass, a tile of the two-step shape whose
+// cells and four cells around them (the reach of two steps) lie inside the grid takes the
+// two-step kernel; every other tile its single-step kind.
+int host_kind(const fdlb_ctx *c, const fdlb_params &p, int shape, int x0, int y0) {
+    const int TX = fdlb::kTileShapes[shape].tx, TY = fdlb::kTileShapes[shape].ty;
+    if (c->tblock == 2 && shape == fdlb::kTwoStepShape && x0 >= 4 && y0 >= 4 && x0 + TX + 4 <= p.nx &&
+        y0 + TY + 4 <= p.ny)
+        return fdlb::kKindTwoStep;
+    return fdlb::tile_kind(x0, y0, TX, TY, p.nx, p.ny, p.bc[2].kind);
+}
+
 void release(fdlb_ctx *c) {
     if (!c) return;
     for (auto &g : c->graph)
@@ -356,11 +375,25 @@ fdlb_status set_tiles(fdlb_ctx *c, int shape, int group) {
         const fdlb_params &p = c->params[i];
         const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
         const int g = std::max(1, std::min(group, ntx));
+        std::vector<int> kind((size_t)ntx * nty);
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx) kind[(size_t)ty * ntx + tx] = host_kind(c, p, shape, tx * TX, ty * TY);
+        auto kind_at = [&](int tx, int ty) {
+            return tx < 0 || ty < 0 || tx >= ntx || ty >= nty ? -1 : kind[(size_t)ty * ntx + tx];
+        };
         for (int gx = 0; gx < ntx; gx += g)
             for (int ty = 0; ty < nty; ++ty)
                 for (int tx = gx; tx < std::min(gx + g, ntx); ++tx) {
-                    const int x0 = tx * TX, y0 = ty * TY;
-                    tiles[fdlb::tile_kind(x0, y0, TX, TY, p.nx, p.ny, p.bc[2].kind)].push_back(Tile{i, x0, y0, 0});
+                    const int kd = kind_at(tx, ty);
+                    int32_t flags = 0;
+                    // a two-step tile whose x or y neighbour takes single steps keeps its
+                    // intermediate step in slot 2 for that neighbour's second step (the
+                    // stencil and the switching function reach no diagonal neighbour)
+                    if (kd == fdlb::kKindTwoStep &&
+                        (kind_at(tx - 1, ty) != kd || kind_at(tx + 1, ty) != kd || kind_at(tx, ty - 1) != kd ||
+                         kind_at(tx, ty + 1) != kd))
+                        flags = fdlb::kTileRing;
+                    tiles[kd].push_back(Tile{i, tx * TX, ty * TY, flags});
                 }
     }
     const int es = edge_shape_for(shape, c->prec);
@@ -408,7 +441,9 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
     size_t need = 0;
     for (int i = 0; i < k; ++i) {
         if (validate(p[i])) return FDLB_EINVAL;
-        if (p[i].precision != p[0].precision || default_shape(p[i]) != default_shape(p[0])) return FDLB_EINVAL;
+        if (p[i].precision != p[0].precision || default_shape(p[i]) != default_shape(p[0]) ||
+            (p[i].tblock == 2) != (p[0].tblock == 2))
+            return FDLB_EINVAL;
         need += layout_of(p[i]).total;
     }
     if (bytes < need) return FDLB_EINVAL;
@@ -418,6 +453,7 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
     c->k = k;
     c->prec = p[0].precision;
     c->shape = default_shape(p[0]);
+    c->tblock = p[0].tblock == 2 ? 2 : 1;
     c->stream = static_cast<hipStream_t>(stream);
     c->params.assign(p, p + k);
     c->is_set.assign(k, 0);
@@ -449,20 +485,21 @@ fdlb_status build(int32_t k, const fdlb_params *p, void *stream, void *arena, si
         I.fplane = L.fplane;
         I.wlen = L.wlen;
         I.prec = c->prec;
-        for (int h = 0; h < 2; ++h) {
+        const int ns = nslots(p[i]);  // slot 2 only with two steps per pass (else null)
+        for (int h = 0; h < ns; ++h) {
             I.f[h] = base + off;
             off += L.f_bytes;
         }
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < ns; ++h) {
             I.P[h] = reinterpret_cast<double *>(base + off);
             off += L.p_bytes;
         }
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < ns; ++h) {
             I.M[h] = reinterpret_cast<double *>(base + off);
             off += L.m_bytes;
         }
         I.mplane = L.mplane;
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < ns; ++h) {
             I.PW[h] = reinterpret_cast<double *>(base + off);
             off += L.w_bytes;
         }
@@ -571,33 +608,111 @@ fdlb_status get_instance_host(fdlb_ctx *c, int i, double *rho, double *ux, doubl
     return check_flag(c);
 }
 
+// The single-step tile kinds in launch order (the largest last, so it can run beside the
+// others); kind 3, the two-step tiles, is launched by launch_pair.
+int main_single_kind(const fdlb_ctx *c) {
+    int main_kd = 0;
+    for (int kd = 0; kd < fdlb::kKindTwoStep; ++kd)
+        if (c->ntiles[kd] > c->ntiles[main_kd]) main_kd = kd;
+    return main_kd;
+}
+
+// One single step of the single-step tile kinds from slot `in` to slot `out` on stream s
+// (the smaller kinds on `side` when it is not null).  With `all`, the two-step tiles take
+// the step too, as interior tiles of the single-step kernel (a lone step of a two-step
+// context); without it they are left to launch_step2.
+fdlb_status single_step(fdlb_ctx *c, int in, int out, hipStream_t s, hipStream_t side, bool all) {
+    const int main_kd = main_single_kind(c);
+    if (all && c->ntiles[fdlb::kKindTwoStep] > 0)
+        HIPCHK(c, fdlb::launch_step(c->prec, c->shape, 0, c->d_insts, c->d_tiles[fdlb::kKindTwoStep],
+                                    c->ntiles[fdlb::kKindTwoStep], fdlb::io_pack(in, out), side ? side : s));
+    for (int kd = fdlb::kKindTwoStep - 1; kd >= 0; --kd)
+        if (c->ntiles[kd] > 0)
+            HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd],
+                                        c->ntiles[kd], fdlb::io_pack(in, out), side && kd != main_kd ? side : s));
+    return FDLB_OK;
+}
+
 // n steps on stream s.  branch: the tile kinds other than the largest go on the side
 // stream (fork and join through events), in a graph capture a parallel branch beside the
-// largest kind; without it every kind runs in turn on s.
+// largest kind; without it every kind runs in turn on s.  With two steps per pass, steps
+// go in pairs: the single-step tiles take slot h to slot 2 (beside the two-step kernel,
+// which takes h to 1 - h and fills slot 2 on its ring tiles), then slot 2 to 1 - h.
 fdlb_status launch_steps(fdlb_ctx *c, int64_t n, hipStream_t s, bool branch = false) {
-    int main_kd = 0, kinds = 0;
-    for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd) {
+    int kinds = 0;
+    for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
         if (c->ntiles[kd] > 0) ++kinds;
-        if (c->ntiles[kd] > c->ntiles[main_kd]) main_kd = kd;
-    }
     branch = branch && c->fork && kinds > 1;
-    for (int64_t t = 0; t < n; ++t) {
-        if (branch) {
-            HIPCHK(c, hipEventRecord(c->ev_fork, s));
-            HIPCHK(c, hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+    auto fork = [&]() -> fdlb_status {
+        HIPCHK(c, hipEventRecord(c->ev_fork, s));
+        HIPCHK(c, hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+        return FDLB_OK;
+    };
+    auto join = [&]() -> fdlb_status {
+        HIPCHK(c, hipEventRecord(c->ev_join, c->side_stream));
+        HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
+        return FDLB_OK;
+    };
+    fdlb_status st;
+    for (int64_t t = 0; t < n;) {
+        const int h = c->half;
+        if (c->tblock == 2 && n - t >= 2) {
+            // first step of the single-step tiles (slot h -> 2) beside the two-step kernel
+            const bool two = c->ntiles[fdlb::kKindTwoStep] > 0;
+            hipStream_t sb = branch && two ? c->side_stream : s;
+            if (sb != s && (st = fork()) != FDLB_OK) return st;
+            if ((st = single_step(c, h, 2, sb, nullptr, false)) != FDLB_OK) return st;
+            if (c->wall_len > 0) HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 2, sb));
+            if (c->ticks) HIPCHK(c, fdlb::launch_tick(c->d_clock, sb));
+            if (two)
+                HIPCHK(c, fdlb::launch_step2(c->d_insts, c->d_tiles[fdlb::kKindTwoStep],
+                                             c->ntiles[fdlb::kKindTwoStep], fdlb::io_pack(h, 1 - h), s));
+            if (sb != s && (st = join()) != FDLB_OK) return st;
+            // second step of the single-step tiles (slot 2 -> 1 - h)
+            if ((st = single_step(c, 2, 1 - h, s, nullptr, false)) != FDLB_OK) return st;
+            t += 2;
+        } else {
+            if (branch && (st = fork()) != FDLB_OK) return st;
+            if ((st = single_step(c, h, 1 - h, s, branch ? c->side_stream : nullptr, true)) != FDLB_OK) return st;
+            if (branch && (st = join()) != FDLB_OK) return st;
+            t += 1;
         }
-        for (int kd = fdlb::kNumTileKinds - 1; kd >= 0; --kd)
-            if (c->ntiles[kd] > 0)
-                HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], c->half,
-                                            branch && kd != main_kd ? c->side_stream : s));
-        if (branch) {
-            HIPCHK(c, hipEventRecord(c->ev_join, c->side_stream));
-            HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
-        }
-        if (c->wall_len > 0) HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - c->half, s));
+        if (c->wall_len > 0) HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - h, s));
         if (c->ticks) HIPCHK(c, fdlb::launch_tick(c->d_clock, s));
         c->half ^= 1;
     }
+    return FDLB_OK;
+}
+
+// One trial launch that does not advance the state (kernel timing, autotuning): kind >= 0
+// launches that tile kind alone from slot h (kind 3: the two-step tiles, two steps); kind -1
+// the whole step, with two steps per pass the pair of launch_steps.  The spare slots are
+// overwritten; the clock is not advanced.  *steps receives the steps it stands for.
+fdlb_status trial_launch(fdlb_ctx *c, int kind, int h, int *steps) {
+    *steps = 1;
+    if (kind == fdlb::kKindTwoStep) {
+        *steps = 2;
+        HIPCHK(c, fdlb::launch_step2(c->d_insts, c->d_tiles[kind], c->ntiles[kind], fdlb::io_pack(h, 1 - h), c->stream));
+        return FDLB_OK;
+    }
+    if (kind >= 0) {
+        HIPCHK(c, fdlb::launch_step(c->prec, kind == 2 ? c->edge_shape : c->shape, kind, c->d_insts, c->d_tiles[kind],
+                                    c->ntiles[kind], fdlb::io_pack(h, 1 - h), c->stream));
+        return FDLB_OK;
+    }
+    fdlb_status st;
+    if (c->tblock == 2) {
+        *steps = 2;
+        if ((st = single_step(c, h, 2, c->stream, nullptr, false)) != FDLB_OK) return st;
+        if (c->wall_len > 0) HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 2, c->stream));
+        if (c->ntiles[fdlb::kKindTwoStep] > 0)
+            HIPCHK(c, fdlb::launch_step2(c->d_insts, c->d_tiles[fdlb::kKindTwoStep], c->ntiles[fdlb::kKindTwoStep],
+                                         fdlb::io_pack(h, 1 - h), c->stream));
+        if ((st = single_step(c, 2, 1 - h, c->stream, nullptr, false)) != FDLB_OK) return st;
+    } else if ((st = single_step(c, h, 1 - h, c->stream, nullptr, true)) != FDLB_OK) {
+        return st;
+    }
+    if (c->wall_len > 0) HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - h, c->stream));
     return FDLB_OK;
 }
 
@@ -861,6 +976,7 @@ fdlb_status fdlb_set_clock(fdlb_ctx *c, int64_t steps) {
 
 fdlb_status fdlb_set_tiling(fdlb_ctx *c, int32_t shape_id, int32_t group) {
     if (!c || shape_id < 1 || shape_id > fdlb::kNumTileShapes || group < 1) return FDLB_EINVAL;
+    if (c->tblock == 2 && shape_id - 1 != fdlb::kTwoStepShape) return FDLB_EINVAL;
     return set_tiles(c, shape_id - 1, group);
 }
 
@@ -880,7 +996,7 @@ int64_t fdlb_tile_cells(const fdlb_ctx *c, int32_t kind) {
         const fdlb_params &p = c->params[i];
         for (int y0 = 0; y0 < p.ny; y0 += TY)
             for (int x0 = 0; x0 < p.nx; x0 += TX)
-                if (fdlb::tile_kind(x0, y0, TX, TY, p.nx, p.ny, p.bc[2].kind) == kind)
+                if (host_kind(c, p, c->shape, x0, y0) == kind)
                     cells += (int64_t)std::min(TX, p.nx - x0) * std::min(TY, p.ny - y0);
     }
     return cells;
@@ -894,33 +1010,39 @@ fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float 
     EventPair ev;
     HIPCHK(c, ev.create());
     const int h = c->half;
-    for (int w = 0; w < 2 + launches; ++w) {
-        if (w == 2) HIPCHK(c, hipEventRecord(ev.e0, c->stream));
-        for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
-            if (c->ntiles[kd] > 0 && (kind < 0 || kd == kind))
-                HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd], h,
-                                            c->stream));
-        if (kind < 0 && c->wall_len > 0)
-            HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - h, c->stream));
+    if (kind >= 0 && c->ntiles[kind] == 0) {
+        *ms_per_launch = 0.0f;
+        return FDLB_OK;
     }
+    // kind -1: `launches` steps (a pair counts two); a kind alone: `launches` launches
+    int per = 1;
+    fdlb_status st;
+    for (int w = 0; w < 2; ++w)
+        if ((st = trial_launch(c, kind, h, &per)) != FDLB_OK) return st;
+    const int units = kind < 0 ? (launches + per - 1) / per : launches;
+    HIPCHK(c, hipEventRecord(ev.e0, c->stream));
+    for (int u = 0; u < units; ++u)
+        if ((st = trial_launch(c, kind, h, &per)) != FDLB_OK) return st;
     HIPCHK(c, hipEventRecord(ev.e1, c->stream));
     HIPCHK(c, hipEventSynchronize(ev.e1));
     float ms = 0.0f;
     HIPCHK(c, hipEventElapsedTime(&ms, ev.e0, ev.e1));
-    *ms_per_launch = ms / (float)launches;
+    *ms_per_launch = ms / (float)(kind < 0 ? units * per : units);
     return FDLB_OK;
 }
 
 fdlb_status fdlb_copy_ceiling(fdlb_ctx *c, int32_t launches, float *ms_per_launch) {
     if (!c || !ms_per_launch || launches < 1) return FDLB_EINVAL;
     if (!c->state_set) return FDLB_ESTATE;
-    if (c->ntiles[0] == 0) return FDLB_EINVAL;
+    // the interior tiles: the single-step ones, or with two steps per pass the two-step ones
+    const int kd = c->ntiles[0] > 0 ? 0 : fdlb::kKindTwoStep;
+    if (c->ntiles[kd] == 0) return FDLB_EINVAL;
     EventPair ev;
     HIPCHK(c, ev.create());
     const int h = c->half;
     for (int w = 0; w < 2 + launches; ++w) {
         if (w == 2) HIPCHK(c, hipEventRecord(ev.e0, c->stream));
-        HIPCHK(c, fdlb::launch_plane_copy(c->prec, c->shape, c->d_insts, c->d_tiles[0], c->ntiles[0], h, c->stream));
+        HIPCHK(c, fdlb::launch_plane_copy(c->prec, c->shape, c->d_insts, c->d_tiles[kd], c->ntiles[kd], h, c->stream));
     }
     HIPCHK(c, hipEventRecord(ev.e1, c->stream));
     HIPCHK(c, hipEventSynchronize(ev.e1));
@@ -943,6 +1065,12 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
         if (groups[i] < 1) return FDLB_EINVAL;
         gr.push_back(groups[i]);
     }
+    if (c->tblock == 2) {
+        // the two-step kernel has one tile shape: only the dispatch groups are tuned
+        for (int s : sh)
+            if (s != fdlb::kTwoStepShape) return FDLB_EINVAL;
+        sh.assign(1, fdlb::kTwoStepShape);
+    }
     if (sh.empty())
         for (int s = 0; s < fdlb::kNumTileShapes; ++s) sh.push_back(s);
     if (gr.empty()) gr = {1, 4, 8, 16, 32};
@@ -959,20 +1087,19 @@ fdlb_status fdlb_autotune(fdlb_ctx *c, int32_t trial_steps, const int32_t *shape
             if (st != FDLB_OK) return st;
             // trial steps read the current half and write the other one without swapping:
             // the state is left exactly as it was
-            for (int w = 0; w < 2 + trial_steps; ++w) {
-                if (w == 2) HIPCHK(c, hipEventRecord(ev.e0, c->stream));
-                for (int kd = 0; kd < fdlb::kNumTileKinds; ++kd)
-                    if (c->ntiles[kd] > 0)
-                        HIPCHK(c, fdlb::launch_step(c->prec, kd == 2 ? c->edge_shape : c->shape, kd, c->d_insts, c->d_tiles[kd], c->ntiles[kd],
-                                                    h, c->stream));
-                if (c->wall_len > 0)
-                    HIPCHK(c, fdlb::launch_wall_pressure(c->d_insts, c->k, c->wall_len, 1 - h, c->stream));
-            }
+            int per = 1;
+            fdlb_status ts;
+            for (int w = 0; w < 2; ++w)
+                if ((ts = trial_launch(c, -1, h, &per)) != FDLB_OK) return ts;
+            const int units = (trial_steps + per - 1) / per;
+            HIPCHK(c, hipEventRecord(ev.e0, c->stream));
+            for (int u = 0; u < units; ++u)
+                if ((ts = trial_launch(c, -1, h, &per)) != FDLB_OK) return ts;
             HIPCHK(c, hipEventRecord(ev.e1, c->stream));
             HIPCHK(c, hipEventSynchronize(ev.e1));
             float ms = 0.0f;
             HIPCHK(c, hipEventElapsedTime(&ms, ev.e0, ev.e1));
-            ms /= (float)trial_steps;
+            ms /= (float)(units * per);
             if (best < 0.0f || ms < best) {
                 best = ms;
                 best_s = s;

@@ -1,6 +1,7 @@
 // fdlb_internal.h -- types shared by the HIP kernels and the host runtime of libfdlb.
 //
-// Layout in HBM (per instance, per ping-pong half h = 0, 1):
+// Layout in HBM (per instance, per buffer slot h = 0, 1 -- the ping-pong halves -- and, for
+// contexts that take two steps per pass, h = 2, the intermediate step's buffer):
 //   f[h]  : 33 planes of ny rows x fpitch elements (float64 or float32), structure of
 //           arrays, x fastest; plane q = 0 is the rest particle, q = 1 + 8(k-1) + (i-1) the
 //           velocity of speed k and direction i pi/4 (Eq. dvm_eq_1).  In the deviation
@@ -11,7 +12,9 @@
 //           (ppitch == fpitch, so one element offset addresses a cell in both).
 //   PW[h] : 4 rows of wlen float64, the pressure of the mirror image of the cells next to
 //           each reflecting side (x-, x+, y-, y+), read by the switching function.
-// The step reads half h and writes half 1 - h.
+// A single step reads slot h and writes slot 1 - h; a two-step pass reads h, keeps the
+// intermediate step of its tiles in LDS (and in slot 2 where single-step tiles need it) and
+// writes 1 - h.  Kernels take the slots packed as io = in | out << 4.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,10 +34,10 @@ struct Inst {
     int64_t fplane;          // elements per f plane (ny * fpitch)
     int32_t bc[4];           // x-, x+, y-, y+
     int32_t wlen, prec;
-    void *f[2];
-    double *P[2];
-    double *M[2];
-    double *PW[2];
+    void *f[3];
+    double *P[3];
+    double *M[3];
+    double *PW[3];
     int64_t mplane;          // elements per moment plane (ny * ppitch)
     int32_t *flag;           // sticky non-physical flag (shared by a batch)
     int32_t *pad_ptr;
@@ -61,22 +64,40 @@ struct Inst {
 };
 
 struct Tile {
-    int32_t inst, x0, y0, pad;
+    int32_t inst, x0, y0, flags;  // flags: kTileRing for two-step tiles beside single-step ones
 };
+// A two-step tile whose x or y neighbour takes single steps: it also stores its intermediate
+// step (values and moments) in slot 2, where that neighbour's second step reads it.
+constexpr int32_t kTileRing = 1;
+
+// Packed input / output buffer slots of a step launch.
+__host__ __device__ constexpr int io_pack(int in, int out) { return in | (out << 4); }
+__host__ __device__ constexpr int io_in(int io) { return io & 15; }
+__host__ __device__ constexpr int io_out(int io) { return io >> 4; }
 
 struct TileShape {
     int tx, ty;
 };
 
 // Tile shapes the step kernel is instantiated for (index = shape id - 1).
-constexpr TileShape kTileShapes[] = {{32, 8}, {64, 4}, {16, 16}, {64, 8}, {16, 4}, {128, 4}, {32, 4}};
+constexpr TileShape kTileShapes[] = {{32, 8}, {64, 4}, {16, 16}, {64, 8}, {16, 4}, {128, 4}, {32, 4}, {16, 8}};
 constexpr int kNumTileShapes = sizeof(kTileShapes) / sizeof(kTileShapes[0]);
 
 // Host-side launchers (fdlb_kernels.hip).  `insts` / `tiles` are device pointers.
-// kind: 0 interior tiles, 1 tube tiles (periodic height == tile height), 2 edge tiles
-constexpr int kNumTileKinds = 3;
-hipError_t launch_step(int prec, int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
+// kind: 0 interior tiles, 1 tube tiles (periodic height == tile height), 2 edge tiles, all
+// one step per launch; 3 two-step tiles (float64, shape kTwoStepShape, their tile and four
+// cells around it inside the grid), two steps per launch
+constexpr int kNumTileKinds = 4;
+constexpr int kKindTwoStep = 3;
+#ifndef FDLB_TWO_STEP_SHAPE
+#define FDLB_TWO_STEP_SHAPE 7
+#endif
+constexpr int kTwoStepShape = FDLB_TWO_STEP_SHAPE;  // 16 x 8: two blocks per CU
+hipError_t launch_step(int prec, int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int io,
                        hipStream_t s);
+// Two steps of the float64 two-step tiles: reads slot io_in, writes slot io_out (and slot 2
+// for ring tiles).
+hipError_t launch_step2(const Inst *insts, const Tile *tiles, int ntiles, int io, hipStream_t s);
 int tile_kind(int x0, int y0, int tx, int ty, int nx, int ny, int bc_y);
 // Plain copy of the stored planes of `tiles` (interior tiles) from half `half` to the other.
 hipError_t launch_plane_copy(int prec, int shape, const Inst *insts, const Tile *tiles, int ntiles, int half,

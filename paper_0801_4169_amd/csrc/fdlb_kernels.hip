@@ -625,8 +625,9 @@ __device__ __forceinline__ S fetch(const Inst &I, const GLOBAL_AS char *fin, siz
 }
 
 template <class S, int TX, int TY, int MODE>
-__device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const Tile &tile, int half,
+__device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const Tile &tile, int io,
                                           StepSmem<S, TX, TY> &sm) {
+    const int bin = io_in(io), bout = io_out(io);
     const Inst &I = insts[tile.inst];
     constexpr int NT = TX * TY;
     constexpr int H0 = MODE == MODE_TUBE ? 4 * TX : 0;  // the tube body loads only the x halo
@@ -640,11 +641,11 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
     const int x = tile.x0 + tx, y = tile.y0 + ty;
     const int nx = I.nx, ny = I.ny;
     const bool valid = MODE != MODE_EDGE || (x < nx && y < ny);
-    const GLOBAL_AS char *fin = (const GLOBAL_AS char *)(I.f[half]);
-    GLOBAL_AS char *fout = (GLOBAL_AS char *)(I.f[1 - half]);
+    const GLOBAL_AS char *fin = (const GLOBAL_AS char *)(I.f[bin]);
+    GLOBAL_AS char *fout = (GLOBAL_AS char *)(I.f[bout]);
     const size_t pb = (size_t)I.fplane * sizeof(S);
-    const double *__restrict__ Pin = I.P[half];
-    double *__restrict__ Pout = I.P[1 - half];
+    const double *__restrict__ Pin = I.P[bin];
+    double *__restrict__ Pout = I.P[bout];
 
     // offsets: bytes for INTERIOR / TUBE, elements (with mapping) for EDGE
     Src own;
@@ -711,7 +712,7 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
         Pym = Pin[ym * I.ppitch + x];
         Pyp = Pin[yp * I.ppitch + x];
     } else {
-        const double *PWin = I.PW[half];
+        const double *PWin = I.PW[bin];
         Pxm = load_P(I, Pin, PWin, x - 1, y, tnow);
         Pxp = load_P(I, Pin, PWin, x + 1, y, tnow);
         Pym = load_P(I, Pin, PWin, x, y - 1, tnow);
@@ -808,7 +809,7 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
     // per workgroup)
     int bad = 0;
     if constexpr (MODE == MODE_EDGE) {
-        if (valid) bad = write_pressures(I, f, x, y, Pout, I.M[1 - half], I.PW[1 - half]);
+        if (valid) bad = write_pressures(I, f, x, y, Pout, I.M[bout], I.PW[bout]);
     } else {
         double n2, jx2, jy2, E2, ux2, uy2, T2, P2;
         moments_of<0>(I, f, n2, jx2, jy2, E2);
@@ -866,8 +867,9 @@ __device__ __forceinline__ void acc_term(const Inst &I, S v, double &n, double &
 // values appear, in ascending q (pair partners q + 4 are held until their turn).
 // ------------------------------------------------------------------------------------
 template <class S, int TX, int TY, int MODE, int PD>
-__device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts, const Tile &tile, int half,
+__device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts, const Tile &tile, int io,
                                                  StepSmem<S, TX, TY> &sm) {
+    const int bin = io_in(io), bout = io_out(io);
     // EDGE: every cell and halo cell goes through the side mapping; the pressures of the
     // mirror images beside walls are left to wall_pressure_kernel (they need the cell's 33
     // new values summed in mirrored order).
@@ -884,8 +886,8 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
     const int x = tile.x0 + tx, y = tile.y0 + ty;
     const int ny = I.ny;
     const bool valid = MODE != MODE_EDGE || (x < I.nx && y < ny);
-    const GLOBAL_AS char *fin = (const GLOBAL_AS char *)(I.f[half]);
-    GLOBAL_AS char *fout = (GLOBAL_AS char *)(I.f[1 - half]);
+    const GLOBAL_AS char *fin = (const GLOBAL_AS char *)(I.f[bin]);
+    GLOBAL_AS char *fout = (GLOBAL_AS char *)(I.f[bout]);
     const size_t pb = (size_t)I.fplane * sizeof(S);
 
     // offsets: bytes for INTERIOR / TUBE, elements (with mapping) for EDGE
@@ -942,19 +944,19 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
     // A2: moments of the cell from the previous step; A3: switching function
     // (an edge tile's idle threads read their clamped cell; M and f planes share the pitch)
     const GLOBAL_AS double *Mc =
-        (const GLOBAL_AS double *)I.M[half] + (MODE == MODE_EDGE ? own.off : y * I.ppitch + x);
+        (const GLOBAL_AS double *)I.M[bin] + (MODE == MODE_EDGE ? own.off : y * I.ppitch + x);
     const double n = Mc[0], ux = Mc[I.mplane], uy = Mc[2 * I.mplane], T = Mc[3 * I.mplane];
     const double P0 = n * T;
     double Pxm, Pxp, Pym, Pyp;
     // the neighbours' pressure: n T of their stored moments (no pressure plane)
     if constexpr (MODE == MODE_EDGE) {
-        const double *Min = I.M[half], *PWin = I.PW[half];
+        const double *Min = I.M[bin], *PWin = I.PW[bin];
         Pxm = load_P_m(I, Min, PWin, x - 1, y, tnow);
         Pxp = load_P_m(I, Min, PWin, x + 1, y, tnow);
         Pym = load_P_m(I, Min, PWin, x, y - 1, tnow);
         Pyp = load_P_m(I, Min, PWin, x, y + 1, tnow);
     } else {
-        const GLOBAL_AS double *Mn = (const GLOBAL_AS double *)I.M[half];
+        const GLOBAL_AS double *Mn = (const GLOBAL_AS double *)I.M[bin];
         const GLOBAL_AS double *MT = Mn + 3 * (size_t)I.mplane;
         const int c = y * I.ppitch + x;
         Pxm = Mn[c - 1] * MT[c - 1];
@@ -1049,13 +1051,13 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
     double ux2, uy2, T2, P2;
     primitive(n2, jx2, jy2, E2, ux2, uy2, T2, P2);
     if (valid) {
-        GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[1 - half] + (y * I.ppitch + x);
+        GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[bout] + (y * I.ppitch + x);
         Mo[0] = n2;
         Mo[I.mplane] = ux2;
         Mo[2 * I.mplane] = uy2;
         Mo[3 * I.mplane] = T2;
         // the pressure plane only for a register-resident edge body, which reads it
-        if constexpr (!stream_edge<S>()) ((GLOBAL_AS double *)I.P[1 - half])[y * I.ppitch + x] = P2;
+        if constexpr (!stream_edge<S>()) ((GLOBAL_AS double *)I.P[bout])[y * I.ppitch + x] = P2;
     }
     const int bad = valid && nonphysical(I, n2, ux2, uy2, T2) ? 1 : 0;
     if (__syncthreads_or(bad) && tid == 0) *I.flag = 1;
@@ -1086,17 +1088,289 @@ constexpr bool stream_edge() {
     return use_stream<S>() && FDLB_STREAM_EDGE != 0;
 }
 
+// Minimum waves per SIMD asked of the step kernels' register allocation (0: the compiler's
+// own choice).  FDLB_STEP_WAVES applies to the float64 and float32 kernels, FDLB_DEV_WAVES
+// to the deviation kernels.
+#ifndef FDLB_STEP_WAVES
+#define FDLB_STEP_WAVES 0
+#endif
+#ifndef FDLB_DEV_WAVES
+#define FDLB_DEV_WAVES 0
+#endif
+#if FDLB_STEP_WAVES > 0
+#define FDLB_STEP_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(FDLB_STEP_WAVES)))
+#else
+#define FDLB_STEP_WAVES_ATTR
+#endif
+#if FDLB_DEV_WAVES > 0
+#define FDLB_DEV_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(FDLB_DEV_WAVES)))
+#else
+#define FDLB_DEV_WAVES_ATTR
+#endif
+
 // One kernel per tile kind, so the common interior kernel gets its own (small) register
 // allocation; the host splits the tile table by kind (same rule as tile_kind below).
 template <class S, int TX, int TY, int MODE>
-__global__ __launch_bounds__(TX *TY) void step_kernel(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
-                                                      int ntiles, int half) {
+__global__ __launch_bounds__(TX *TY) FDLB_STEP_WAVES_ATTR void step_kernel(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
+                                                      int ntiles, int io) {
     __shared__ StepSmem<S, TX, TY> sm;
     const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
     if constexpr (!use_stream<S>() || (MODE == MODE_EDGE && !stream_edge<S>()))
-        step_body<S, TX, TY, MODE>(insts, tile, half, sm);
+        step_body<S, TX, TY, MODE>(insts, tile, io, sm);
     else
-        step_body_stream<S, TX, TY, MODE, FDLB_PREFETCH>(insts, tile, half, sm);
+        step_body_stream<S, TX, TY, MODE, FDLB_PREFETCH>(insts, tile, io, sm);
+}
+
+// ------------------------------------------------------------------------------------
+// Two steps per pass (float64, tiles whose tile and four cells around it lie inside the
+// grid).  The stencil of Eq. (dis_eq1) reaches two cells, so two steps of a TX x TY tile
+// need step n on the tile and four cells around it (R0) and step n + 1 on the tile and the
+// two-cell cross around it (R1).  Phase 1 streams the planes of step n through LDS and takes
+// step n + 1 on R1 into LDS (all 33 planes), phase 2 takes step n + 2 on the tile from
+// there.  Each cell-update runs the same functions in the same order as the single-step
+// streaming body (moments of step n from the stored moment planes, the neighbours'
+// pressure as n T of their moments, the new moments summed in ascending q), so the result
+// is that of two single steps bit for bit, for half the memory traffic.
+// ------------------------------------------------------------------------------------
+// The staged planes use an odd row pitch (TX + 9 doubles): lanes that walk down a halo
+// column then fall on distinct LDS banks.
+template <int TX, int TY>
+struct Step2Smem {
+    double stage[2][2][TY + 8][TX + 9];  // planes of step n on R0 (a pair per stage, double buffered)
+    double f1[NQ][TY + 4][TX + 4];       // step n + 1 on R1
+    double P1[TY + 2][TX + 2];           // its pressure on the tile and the one-cell ring
+};
+
+template <int TX, int TY>
+constexpr int step2_threads() {
+    return (TX * TY + 4 * (TX + TY) + 63) / 64 * 64;  // one thread per cell of R1
+}
+
+template <int TX, int TY, int PD>
+__device__ __forceinline__ void step2_body(const Inst *__restrict__ insts, const Tile &tile, int io,
+                                           Step2Smem<TX, TY> &sm) {
+    constexpr int NT = step2_threads<TX, TY>();
+    constexpr int NTILE = TX * TY;
+    constexpr int NR1 = NTILE + 4 * (TX + TY);
+    constexpr int R0W = TX + 8, R0H = TY + 8, NR0 = R0W * R0H, R0P = TX + 9;  // R0P: LDS row pitch
+    constexpr int NSL = (NR0 + NT - 1) / NT;  // R0 cells each thread stages per plane
+    const Inst &I = insts[tile.inst];
+    const int bin = io_in(io), bout = io_out(io);
+    const bool ring = (tile.flags & kTileRing) != 0;
+    const int tid = threadIdx.x;
+
+    // this thread's cell of R1 (tile-local; -2..TX+1, -2..TY+1, cross-shaped)
+    int lx, ly;
+    if (tid < NTILE) {
+        lx = tid % TX;
+        ly = tid / TX;
+    } else {
+        const int hid = tid - NTILE;
+        if (hid < 4 * TX) {
+            const int r = hid / TX;
+            lx = hid % TX;
+            ly = r < 2 ? r - 2 : TY + r - 2;
+        } else {
+            const int h2 = min(hid - 4 * TX, 4 * TY - 1);  // threads past R1 take its last cell
+            const int c = h2 / TY;
+            ly = h2 % TY;
+            lx = c < 2 ? c - 2 : TX + c - 2;
+        }
+    }
+    const bool active = tid < NR1;
+    const GLOBAL_AS char *fin = (const GLOBAL_AS char *)(I.f[bin]);
+    GLOBAL_AS char *fout = (GLOBAL_AS char *)(I.f[bout]);
+    GLOBAL_AS char *fmid = (GLOBAL_AS char *)(I.f[2]);
+    const size_t pb = (size_t)I.fplane * sizeof(double);
+
+    // R0 staging: slot j of this thread is cell r0 = tid + j NT of the (TX+8) x (TY+8)
+    // rectangle; its corners beyond the stencils' reach are loaded from a clamped cell and
+    // never read (the loads stay unconditional)
+    int r0off[NSL], r0l[NSL];
+#pragma unroll
+    for (int j = 0; j < NSL; ++j) {
+        const int r0 = min(tid + j * NT, NR0 - 1);
+        r0l[j] = tid + j * NT < NR0 ? (r0 / R0W) * R0P + r0 % R0W : -1;
+        const int X = tile.x0 + r0 % R0W - 4, Y = tile.y0 + r0 / R0W - 4;
+        r0off[j] = (Y * I.fpitch + X) * (int)sizeof(double);
+    }
+    double pr[PD][2][NSL];
+    auto load_stage = [&](auto stc, const Inst &Is, size_t pbs) {
+        constexpr int st = decltype(stc)::value;
+        constexpr int slot = st % PD, qa = stage_qa(st), qb = stage_qb(st);
+#pragma unroll
+        for (int j = 0; j < NSL; ++j) {
+            pr[slot][0][j] = *reinterpret_cast<const GLOBAL_AS double *>(fin + (size_t)qa * pbs + (uint32_t)r0off[j]);
+            if constexpr (qb >= 0)
+                pr[slot][1][j] = *reinterpret_cast<const GLOBAL_AS double *>(fin + (size_t)qb * pbs + (uint32_t)r0off[j]);
+        }
+    };
+    static_for<0, PD>([&](auto stc) { load_stage(stc, I, pb); });
+
+    // phase 1 set-up: moments of step n from the moment planes, switching function from the
+    // neighbours' n T (all of R1's neighbours lie inside the grid)
+    const int x = tile.x0 + lx, y = tile.y0 + ly;
+    const int c = y * I.ppitch + x;
+    const GLOBAL_AS double *Mn = (const GLOBAL_AS double *)I.M[bin];
+    const GLOBAL_AS double *MT = Mn + 3 * (size_t)I.mplane;
+    const double n = Mn[c], ux = Mn[c + I.mplane], uy = Mn[c + 2 * I.mplane], T = MT[c];
+    const double P0 = n * T;
+    const double Pxm = Mn[c - 1] * MT[c - 1];
+    const double Pxp = Mn[c + 1] * MT[c + 1];
+    const double Pym = Mn[c - I.ppitch] * MT[c - I.ppitch];
+    const double Pyp = Mn[c + I.ppitch] * MT[c + I.ppitch];
+    CellD cell;
+    {
+        const double ax = av_coeff(I.lam, Pxm, P0, Pxp, ux, I.dt, I.dx);
+        const double ay = av_coeff(I.lam, Pym, P0, Pyp, uy, I.dt, I.dy);
+        Coef C;
+        equilibrium_coefs(I, n, ux, uy, T, C);
+        make_cell(C, ux, uy, ax, ay, I.dtau, cell);
+    }
+    const int o0 = (ly + 4) * R0P + (lx + 4);  // own cell in the R0 frame
+    const int o1x = lx + 2, o1y = ly + 2;         // own cell in the R1 frame
+    const uint32_t own_b = (uint32_t)(c * (int)sizeof(double));
+    const bool mid_store = ring && tid < NTILE;
+
+    auto update0 = [&](auto qc, const Inst &Is, const double *pl, double feq) {
+        constexpr int q = decltype(qc)::value;
+        return update_f64<q>(Is, cell, pl[o0], feq, pl[o0 - 2], pl[o0 - 1], pl[o0 + 1], pl[o0 + 2], pl[o0 - 2 * R0P],
+                             pl[o0 - R0P], pl[o0 + R0P], pl[o0 + 2 * R0P]);
+    };
+    double n1 = 0.0, jx1 = 0.0, jy1 = 0.0, E1 = 0.0;
+    double hold[3];
+    int b = 0;
+    static_for<0, NSTAGE>([&](auto stc) {
+        constexpr int st = decltype(stc)::value;
+        constexpr int slot = st % PD, qa = stage_qa(st), qb = stage_qb(st);
+        const Inst &Is = insts[opaque(tile.inst)];
+        const size_t pbs = opaque(pb);
+        double *pa = &sm.stage[b][0][0][0];
+        double *pbuf = &sm.stage[b][1][0][0];
+#pragma unroll
+        for (int j = 0; j < NSL; ++j)
+            if (r0l[j] >= 0) {
+                pa[r0l[j]] = pr[slot][0][j];
+                if constexpr (qb >= 0) pbuf[r0l[j]] = pr[slot][1][j];
+            }
+        __syncthreads();
+        if constexpr (st + PD < NSTAGE) load_stage(std::integral_constant<int, st + PD>{}, Is, pbs);
+        if constexpr (qb < 0) {
+            const double fn = update0(std::integral_constant<int, 0>{}, Is, pa, cell.nF[0] * cell.c0);
+            if (active) sm.f1[0][o1y][o1x] = fn;
+            if (mid_store) store_out(reinterpret_cast<GLOBAL_AS double *>(fmid + own_b), fn);
+            acc_term<0>(Is, fn, n1, jx1, jy1, E1);
+        } else {
+            double fea, feb;
+            feq_pair_f64<qa>(Is, cell, fea, feb);
+            const double fna = update0(std::integral_constant<int, qa>{}, Is, pa, fea);
+            const double fnb = update0(std::integral_constant<int, qb>{}, Is, pbuf, feb);
+            if (active) {
+                sm.f1[qa][o1y][o1x] = fna;
+                sm.f1[qb][o1y][o1x] = fnb;
+            }
+            if (mid_store) {
+                store_out(reinterpret_cast<GLOBAL_AS double *>(fmid + (size_t)qa * pbs + own_b), fna);
+                store_out(reinterpret_cast<GLOBAL_AS double *>(fmid + (size_t)qb * pbs + own_b), fnb);
+            }
+            constexpr int j = (st - 1) % 4;
+            acc_term<qa>(Is, fna, n1, jx1, jy1, E1);
+            if constexpr (j < 3) {
+                hold[j] = fnb;
+            } else {
+                acc_term<qa + 1>(Is, hold[0], n1, jx1, jy1, E1);
+                acc_term<qa + 2>(Is, hold[1], n1, jx1, jy1, E1);
+                acc_term<qa + 3>(Is, hold[2], n1, jx1, jy1, E1);
+                acc_term<qb>(Is, fnb, n1, jx1, jy1, E1);
+            }
+        }
+        b ^= 1;
+    });
+
+    // moments of step n + 1; pressure ring for the second switching function
+    double ux1, uy1, T1, P1;
+    primitive(n1, jx1, jy1, E1, ux1, uy1, T1, P1);
+    const double P1m = n1 * T1;  // n T of the moments, as the next step reads them
+    if (active && lx >= -1 && lx <= TX && ly >= -1 && ly <= TY) sm.P1[ly + 1][lx + 1] = P1m;
+    int bad = tid < NTILE && nonphysical(I, n1, ux1, uy1, T1) ? 1 : 0;
+    if (mid_store) {
+        GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[2] + c;
+        Mo[0] = n1;
+        Mo[I.mplane] = ux1;
+        Mo[2 * I.mplane] = uy1;
+        Mo[3 * I.mplane] = T1;
+    }
+    __syncthreads();
+
+    // phase 2: step n + 2 on the tile from LDS
+    if (tid < NTILE) {
+        CellD cell2;
+        {
+            const double ax = av_coeff(I.lam, sm.P1[ly + 1][lx], P1m, sm.P1[ly + 1][lx + 2], ux1, I.dt, I.dx);
+            const double ay = av_coeff(I.lam, sm.P1[ly][lx + 1], P1m, sm.P1[ly + 2][lx + 1], uy1, I.dt, I.dy);
+            Coef C;
+            equilibrium_coefs(I, n1, ux1, uy1, T1, C);
+            make_cell(C, ux1, uy1, ax, ay, I.dtau, cell2);
+        }
+        auto update1 = [&](auto qc, const Inst &Is, double feq) {
+            constexpr int q = decltype(qc)::value;
+            const double(&pl)[TY + 4][TX + 4] = sm.f1[q];
+            return update_f64<q>(Is, cell2, pl[o1y][o1x], feq, pl[o1y][o1x - 2], pl[o1y][o1x - 1], pl[o1y][o1x + 1],
+                                 pl[o1y][o1x + 2], pl[o1y - 2][o1x], pl[o1y - 1][o1x], pl[o1y + 1][o1x],
+                                 pl[o1y + 2][o1x]);
+        };
+        double n2 = 0.0, jx2 = 0.0, jy2 = 0.0, E2 = 0.0;
+        double hold2[3];
+        static_for<0, NSTAGE>([&](auto stc) {
+            constexpr int st = decltype(stc)::value;
+            constexpr int qa = stage_qa(st), qb = stage_qb(st);
+            const Inst &Is = insts[opaque(tile.inst)];
+            const size_t pbs = opaque(pb);
+            if constexpr (qb < 0) {
+                const double fn = update1(std::integral_constant<int, 0>{}, Is, cell2.nF[0] * cell2.c0);
+                store_out(reinterpret_cast<GLOBAL_AS double *>(fout + own_b), fn);
+                acc_term<0>(Is, fn, n2, jx2, jy2, E2);
+            } else {
+                double fea, feb;
+                feq_pair_f64<qa>(Is, cell2, fea, feb);
+                const double fna = update1(std::integral_constant<int, qa>{}, Is, fea);
+                const double fnb = update1(std::integral_constant<int, qb>{}, Is, feb);
+                store_out(reinterpret_cast<GLOBAL_AS double *>(fout + (size_t)qa * pbs + own_b), fna);
+                store_out(reinterpret_cast<GLOBAL_AS double *>(fout + (size_t)qb * pbs + own_b), fnb);
+                constexpr int j = (st - 1) % 4;
+                acc_term<qa>(Is, fna, n2, jx2, jy2, E2);
+                if constexpr (j < 3) {
+                    hold2[j] = fnb;
+                } else {
+                    acc_term<qa + 1>(Is, hold2[0], n2, jx2, jy2, E2);
+                    acc_term<qa + 2>(Is, hold2[1], n2, jx2, jy2, E2);
+                    acc_term<qa + 3>(Is, hold2[2], n2, jx2, jy2, E2);
+                    acc_term<qb>(Is, fnb, n2, jx2, jy2, E2);
+                }
+            }
+        });
+        double ux2, uy2, T2, P2;
+        primitive(n2, jx2, jy2, E2, ux2, uy2, T2, P2);
+        GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[bout] + c;
+        Mo[0] = n2;
+        Mo[I.mplane] = ux2;
+        Mo[2 * I.mplane] = uy2;
+        Mo[3 * I.mplane] = T2;
+        bad |= nonphysical(I, n2, ux2, uy2, T2) ? 1 : 0;
+    }
+    if (__syncthreads_or(bad) && tid == 0) *I.flag = 1;
+}
+
+#ifndef FDLB_STEP2_PREFETCH
+#define FDLB_STEP2_PREFETCH 2  // stages of look-ahead of the two-step body's first phase
+#endif
+template <int TX, int TY>
+__global__ __launch_bounds__((step2_threads<TX, TY>())) void step2_kernel(const Inst *__restrict__ insts,
+                                                                       const Tile *__restrict__ tiles, int ntiles,
+                                                                       int io) {
+    __shared__ Step2Smem<TX, TY> sm;
+    const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
+    step2_body<TX, TY, FDLB_STEP2_PREFETCH>(insts, tile, io, sm);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1261,10 +1535,13 @@ __device__ __forceinline__ void pin(double &v) { asm volatile("" : "+v"(v)); }
 // indexed by halo id: the halo threads keep them here rather than in registers.
 constexpr int kHaloFields = 12;
 
+// P holds the pressure of the tile and its one-cell ring only (the switching function reads
+// the neighbours at +-1), which keeps a 32 x 8 tile's block within 32 KiB: five blocks fit
+// the 160 KiB of a CU.
 template <int TX, int TY, int UPS, int NHC>
 struct DevSmem {
     double buf[2][2 * UPS][TY + 4][TX + 4];
-    double P[(TY + 4) * (TX + 4)];
+    double P[(TY + 2) * (TX + 2)];
     double hc[kHaloFields][NHC];
 };
 
@@ -1294,8 +1571,9 @@ __device__ __forceinline__ void dev_feq_pair_lds(const Inst &I, const double (&h
 
 // One body for the three tile kinds (side mapping only in EDGE tiles).
 template <int TX, int TY, int MODE, int PD, int UPS>
-__device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, const Tile &tile, int half,
+__device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, const Tile &tile, int io,
                                               DevSmem<TX, TY, UPS, dev_halo_cells<TX, TY, MODE>()> &sm) {
+    const int bin = io_in(io), bout = io_out(io);
     const Inst &I = insts[tile.inst];
     constexpr int NT = TX * TY;
     constexpr int H0 = MODE == MODE_TUBE ? 4 * TX : 0;  // the tube body loads only the x halo
@@ -1307,10 +1585,10 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
     const int tx = tid % TX, ty = tid / TX;
     const int x = tile.x0 + tx, y = tile.y0 + ty;
     const bool valid = MODE != MODE_EDGE || (x < I.nx && y < I.ny);
-    const GLOBAL_AS char *gin = (const GLOBAL_AS char *)(I.f[half]);
-    GLOBAL_AS char *gout = (GLOBAL_AS char *)(I.f[1 - half]);
+    const GLOBAL_AS char *gin = (const GLOBAL_AS char *)(I.f[bin]);
+    GLOBAL_AS char *gout = (GLOBAL_AS char *)(I.f[bout]);
     const size_t pb = (size_t)I.fplane * sizeof(float);
-    const GLOBAL_AS double *Min = (const GLOBAL_AS double *)I.M[half];
+    const GLOBAL_AS double *Min = (const GLOBAL_AS double *)I.M[bin];
 
     Src own;
     double tnow = 0.0;
@@ -1389,12 +1667,20 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
             if (ty < 2) pl[own_l + TY * LW] = v;
         }
     };
+    // pressure ring: index of local cell (lx, ly), -1 <= lx <= TX, -1 <= ly <= TY
+    constexpr int PWD = TX + 2;
+    const int own_p = (ty + 1) * PWD + (tx + 1);
     DevCell dc;
     {
         double n, ux, uy, T;
         load_m<MODE>(I, Min, own, n, ux, uy, T);
         dev_cell(I, n, ux, uy, T, dc);
-        put(sm.P, n * T);
+        const double P0 = n * T;
+        sm.P[own_p] = P0;
+        if constexpr (MODE == MODE_TUBE) {
+            if (ty == TY - 1) sm.P[own_p - TY * PWD] = P0;  // y = -1 is row ny - 1
+            if (ty == 0) sm.P[own_p + TY * PWD] = P0;       // y = ny is row 0
+        }
     }
     constexpr int NH = dev_halo_cells<TX, TY, MODE>();
 #pragma unroll
@@ -1415,7 +1701,9 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
                 sm.hc[6][h] = d.uy;
 #pragma unroll
                 for (int k = 0; k < 5; ++k) sm.hc[7 + k][h] = d.nF[k];
-                sm.P[hl[j]] = n * T;
+                // only the ring one cell out is read by the switching function
+                const int lx = hl[j] % LW - 2, ly = hl[j] / LW - 2;
+                if (lx >= -1 && lx <= TX && ly >= -1 && ly <= TY) sm.P[(ly + 1) * PWD + (lx + 1)] = n * T;
             }
         }
 
@@ -1457,9 +1745,9 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
         __syncthreads();
         if constexpr (st == 0) {
             // switching function from the neighbours' P (written before the first barrier)
-            const double P0 = sm.P[own_l];
-            ax = av_dev(Is.lam, sm.P[own_l - 1], P0, sm.P[own_l + 1], dc.ux, Is.cdx);
-            ay = av_dev(Is.lam, sm.P[own_l - LW], P0, sm.P[own_l + LW], dc.uy, Is.cdy);
+            const double P0 = sm.P[own_p];
+            ax = av_dev(Is.lam, sm.P[own_p - 1], P0, sm.P[own_p + 1], dc.ux, Is.cdx);
+            ay = av_dev(Is.lam, sm.P[own_p - PWD], P0, sm.P[own_p + PWD], dc.uy, Is.cdy);
         }
         if constexpr (st + PD < NSTG) load_stage(std::integral_constant<int, st + PD>{}, Is, pbs);
         static_for<0, UPS>([&](auto ic) {
@@ -1506,7 +1794,7 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
             if constexpr (qb >= 0)
                 store_out(reinterpret_cast<GLOBAL_AS float *>(gout + (size_t)qb * pbs + own_b), gb);
         });
-        GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[1 - half] + (y * I.ppitch + x);
+        GLOBAL_AS double *Mo = (GLOBAL_AS double *)I.M[bout] + (y * I.ppitch + x);
         Mo[0] = n2;
         Mo[I.mplane] = ux2;
         Mo[2 * I.mplane] = uy2;
@@ -1522,11 +1810,11 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
 #define FDLB_DEV_UPS 1       // plane units (rest plane or plane pair) per stage
 #endif
 template <int TX, int TY, int MODE>
-__global__ __launch_bounds__(TX *TY) void step_kernel_dev(const Inst *__restrict__ insts,
-                                                          const Tile *__restrict__ tiles, int ntiles, int half) {
+__global__ __launch_bounds__(TX *TY) FDLB_DEV_WAVES_ATTR void step_kernel_dev(const Inst *__restrict__ insts,
+                                                          const Tile *__restrict__ tiles, int ntiles, int io) {
     __shared__ DevSmem<TX, TY, FDLB_DEV_UPS, dev_halo_cells<TX, TY, MODE>()> sm;
     const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
-    step_body_dev<TX, TY, MODE, FDLB_DEV_PREFETCH, FDLB_DEV_UPS>(insts, tile, half, sm);
+    step_body_dev<TX, TY, MODE, FDLB_DEV_PREFETCH, FDLB_DEV_UPS>(insts, tile, io, sm);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1754,60 +2042,61 @@ __global__ __launch_bounds__(kDiagBlock) void diag_final_kernel(const double *__
 // Launchers
 // ------------------------------------------------------------------------------------
 template <class S, int SHAPE, int MODE>
-static hipError_t launch_step_m(const Inst *insts, const Tile *tiles, int ntiles, int half, hipStream_t s) {
+static hipError_t launch_step_m(const Inst *insts, const Tile *tiles, int ntiles, int io, hipStream_t s) {
     constexpr int TX = kTileShapes[SHAPE].tx, TY = kTileShapes[SHAPE].ty;
     hipLaunchKernelGGL((step_kernel<S, TX, TY, MODE>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles, ntiles,
-                       half);
+                       io);
     return hipGetLastError();
 }
 
 template <class S, int SHAPE>
-static hipError_t launch_step_t(int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
+static hipError_t launch_step_t(int kind, const Inst *insts, const Tile *tiles, int ntiles, int io,
                                 hipStream_t s) {
-    if (kind == MODE_INTERIOR) return launch_step_m<S, SHAPE, MODE_INTERIOR>(insts, tiles, ntiles, half, s);
-    if (kind == MODE_TUBE) return launch_step_m<S, SHAPE, MODE_TUBE>(insts, tiles, ntiles, half, s);
-    return launch_step_m<S, SHAPE, MODE_EDGE>(insts, tiles, ntiles, half, s);
+    if (kind == MODE_INTERIOR) return launch_step_m<S, SHAPE, MODE_INTERIOR>(insts, tiles, ntiles, io, s);
+    if (kind == MODE_TUBE) return launch_step_m<S, SHAPE, MODE_TUBE>(insts, tiles, ntiles, io, s);
+    return launch_step_m<S, SHAPE, MODE_EDGE>(insts, tiles, ntiles, io, s);
 }
 
 // Deviation layout: one kernel per tile kind, as for the other storages.
 template <class S, int SHAPE>
-static hipError_t launch_step_dev(int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
+static hipError_t launch_step_dev(int kind, const Inst *insts, const Tile *tiles, int ntiles, int io,
                                   hipStream_t s) {
     constexpr int TX = kTileShapes[SHAPE].tx, TY = kTileShapes[SHAPE].ty;
     if (kind == MODE_INTERIOR)
         hipLaunchKernelGGL((step_kernel_dev<TX, TY, MODE_INTERIOR>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles,
-                           ntiles, half);
+                           ntiles, io);
     else if (kind == MODE_TUBE)
         hipLaunchKernelGGL((step_kernel_dev<TX, TY, MODE_TUBE>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles,
-                           ntiles, half);
+                           ntiles, io);
     else
         hipLaunchKernelGGL((step_kernel_dev<TX, TY, MODE_EDGE>), dim3(ntiles), dim3(TX * TY), 0, s, insts, tiles,
-                           ntiles, half);
+                           ntiles, io);
     return hipGetLastError();
 }
 
 struct DevTag {};
 
 template <class S, int SHAPE>
-static hipError_t launch_step_any(int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
+static hipError_t launch_step_any(int kind, const Inst *insts, const Tile *tiles, int ntiles, int io,
                                   hipStream_t s) {
     if constexpr (std::is_same<S, DevTag>::value)
-        return launch_step_dev<S, SHAPE>(kind, insts, tiles, ntiles, half, s);
+        return launch_step_dev<S, SHAPE>(kind, insts, tiles, ntiles, io, s);
     else
-        return launch_step_t<S, SHAPE>(kind, insts, tiles, ntiles, half, s);
+        return launch_step_t<S, SHAPE>(kind, insts, tiles, ntiles, io, s);
 }
 
 template <class S>
-static hipError_t launch_step_p(int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
+static hipError_t launch_step_p(int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int io,
                                 hipStream_t s) {
     switch (shape) {
-    case 0: return launch_step_any<S, 0>(kind, insts, tiles, ntiles, half, s);
-    case 1: return launch_step_any<S, 1>(kind, insts, tiles, ntiles, half, s);
-    case 2: return launch_step_any<S, 2>(kind, insts, tiles, ntiles, half, s);
-    case 3: return launch_step_any<S, 3>(kind, insts, tiles, ntiles, half, s);
-    case 4: return launch_step_any<S, 4>(kind, insts, tiles, ntiles, half, s);
-    case 5: return launch_step_any<S, 5>(kind, insts, tiles, ntiles, half, s);
-    case 6: return launch_step_any<S, 6>(kind, insts, tiles, ntiles, half, s);
+    case 0: return launch_step_any<S, 0>(kind, insts, tiles, ntiles, io, s);
+    case 1: return launch_step_any<S, 1>(kind, insts, tiles, ntiles, io, s);
+    case 2: return launch_step_any<S, 2>(kind, insts, tiles, ntiles, io, s);
+    case 3: return launch_step_any<S, 3>(kind, insts, tiles, ntiles, io, s);
+    case 4: return launch_step_any<S, 4>(kind, insts, tiles, ntiles, io, s);
+    case 5: return launch_step_any<S, 5>(kind, insts, tiles, ntiles, io, s);
+    case 6: return launch_step_any<S, 6>(kind, insts, tiles, ntiles, io, s);
+    case 7: return launch_step_any<S, 7>(kind, insts, tiles, ntiles, io, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1854,6 +2143,7 @@ static hipError_t launch_copy_p(int shape, const Inst *insts, const Tile *tiles,
     case 4: return launch_copy_s<S, 4>(insts, tiles, ntiles, half, s);
     case 5: return launch_copy_s<S, 5>(insts, tiles, ntiles, half, s);
     case 6: return launch_copy_s<S, 6>(insts, tiles, ntiles, half, s);
+    case 7: return launch_copy_s<S, 7>(insts, tiles, ntiles, half, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1866,12 +2156,20 @@ hipError_t launch_plane_copy(int prec, int shape, const Inst *insts, const Tile 
     return launch_copy_p<float>(shape, insts, tiles, ntiles, half, s);
 }
 
-hipError_t launch_step(int prec, int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int half,
+hipError_t launch_step2(const Inst *insts, const Tile *tiles, int ntiles, int io, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    constexpr int TX = kTileShapes[kTwoStepShape].tx, TY = kTileShapes[kTwoStepShape].ty;
+    hipLaunchKernelGGL((step2_kernel<TX, TY>), dim3(ntiles), dim3(step2_threads<TX, TY>()), 0, s, insts, tiles,
+                       ntiles, io);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int prec, int shape, int kind, const Inst *insts, const Tile *tiles, int ntiles, int io,
                        hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    if (prec == PREC_F64) return launch_step_p<double>(shape, kind, insts, tiles, ntiles, half, s);
-    if (prec == PREC_DEV) return launch_step_p<DevTag>(shape, kind, insts, tiles, ntiles, half, s);
-    return launch_step_p<float>(shape, kind, insts, tiles, ntiles, half, s);
+    if (prec == PREC_F64) return launch_step_p<double>(shape, kind, insts, tiles, ntiles, io, s);
+    if (prec == PREC_DEV) return launch_step_p<DevTag>(shape, kind, insts, tiles, ntiles, io, s);
+    return launch_step_p<float>(shape, kind, insts, tiles, ntiles, io, s);
 }
 
 int tile_kind(int x0, int y0, int tx, int ty, int nx, int ny, int bc_y) {

@@ -141,3 +141,14 @@ def test_largest_planes():
     assert B.fdlb_required_bytes(_sod_params(nx=16385, ny=16383)) == 0   # padded to 16416
     assert B.fdlb_required_bytes(_sod_params(nx=16385, ny=16383, precision=B.FDLB_F32)) > 0
     assert B.fdlb_required_bytes(_sod_params(nx=1 << 14, ny=(1 << 14) + 1, precision=B.FDLB_F32)) == 0
+
+
+def test_two_step_passes_take_a_third_buffer_and_float64_only():
+    from paper_0801_4169_amd import _binding as B
+    one = B.fdlb_required_bytes(_sod_params())
+    two = B.fdlb_required_bytes(_sod_params(tblock=2))
+    assert two * 2 == one * 3  # three buffer slots instead of two
+    assert B.fdlb_required_bytes(_sod_params(tblock=3)) == 0
+    assert B.fdlb_required_bytes(_sod_params(tblock=-1)) == 0
+    assert B.fdlb_required_bytes(_sod_params(tblock=2, precision=B.FDLB_F32)) == 0
+    assert B.fdlb_required_bytes(_sod_params(tblock=2, precision=B.FDLB_F32_DEV)) == 0
