@@ -235,6 +235,39 @@ fdlb_status fdlb_time_kernel(fdlb_ctx *c, int32_t kind, int32_t launches, float 
  * steps).  FDLB_EINVAL without interior tiles; requires a state (FDLB_ESTATE).  Syncs. */
 fdlb_status fdlb_copy_ceiling(fdlb_ctx *c, int32_t launches, float *ms_per_launch);
 
+/* ---- Stability sweep (Sec. 4) --------------------------------------------------------- */
+/* A uniform equilibrium and the scheme's parameters for the von Neumann analysis of Sec. 4:
+ * one step of Eq. (dis_eq1) multiplies a Fourier mode exp(i phi x / dx) along x of the 33
+ * perturbation amplitudes by the amplification matrix of Eq. (gi_j_eq),
+ *   G(phi) = (1 - dt/tau + lines I-IV at phi) I + (dt/tau) d f^eq / d f,
+ * with the Jacobian of Eq. (pian_fki_eq) taken in closed form and the switching function
+ * of line IV frozen at `theta` (Eq. add4 gives zero on a uniform state).  `lines` selects
+ * lines I..IV of Eq. (dis_eq1) as bits 0..3 (15: the full scheme), as in Figs. 2-6. */
+typedef struct {
+    double rho, ux, uy, T;   /* the uniform state */
+    double dx, dt, tau;      /* > 0 */
+    double theta;            /* frozen switching function of line IV */
+    double v[4];             /* speeds v1..v4, distinct and > 0 */
+    int32_t lines;           /* 0..15 */
+    int32_t pad_;
+} fdlb_vn_case;
+
+/* Spectral radius max |omega| of G(phi_p) for every case c and phase p, computed on the GPU
+ * in double-double arithmetic (about 32 significant digits: these matrices are strongly
+ * non-normal at high Mach number, and float64 eigenvalues are wrong in the third digit),
+ * by a Householder reduction to Hessenberg form and the shifted QR algorithm, one
+ * wavefront per matrix.  `cases`: ncases host structs; `phis`: nphi host phases (radians);
+ * `radius`: host output of ncases * nphi values, case-major (NaN where the iteration did
+ * not converge).  Allocates and frees its own device buffers and syncs `stream` (NULL: the
+ * null stream).  Errors: FDLB_EINVAL (sizes, a non-positive rho, T, dx, dt, tau or speed,
+ * equal speeds, lines outside 0..15, more than 2^24 matrices), FDLB_ENOMEM, FDLB_EDEVICE. */
+fdlb_status fdlb_vn_sweep(const fdlb_vn_case *cases, int32_t ncases, const double *phis, int32_t nphi,
+                          double *radius, void *stream);
+/* The matrix G(phi) itself for one case: 33 x 33 row-major entries of four float64 each
+ * (real part as a double-double hi, lo, then the imaginary part hi, lo) into `matrix`
+ * (4 * 33 * 33 host doubles).  Same errors as fdlb_vn_sweep.  Syncs. */
+fdlb_status fdlb_vn_matrix(const fdlb_vn_case *c, double phi, double *matrix, void *stream);
+
 /* ---- Batched ensembles ------------------------------------------------------------- */
 /* k independent problems of possibly different size and parameters advanced together:
  * every step is one launch over the tiles of all instances.  All instances must share

@@ -49,6 +49,13 @@ class fdlb_params(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("lines", ctypes.c_int32), ("tblock", ctypes.c_int32)]
 
 
+class fdlb_vn_case(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("ux", ctypes.c_double), ("uy", ctypes.c_double), ("T", ctypes.c_double),
+                ("dx", ctypes.c_double), ("dt", ctypes.c_double), ("tau", ctypes.c_double),
+                ("theta", ctypes.c_double), ("v", ctypes.c_double * 4), ("lines", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
 class FdlbError(RuntimeError):
     def __init__(self, status, msg=""):
         self.status = status
@@ -89,6 +96,9 @@ _sigs = {
     "fdlb_tile_cells": (ctypes.c_int64, [_CTX, ctypes.c_int32]),
     "fdlb_time_kernel": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
     "fdlb_copy_ceiling": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "fdlb_vn_sweep": (ctypes.c_int, [ctypes.POINTER(fdlb_vn_case), ctypes.c_int32, _DP, ctypes.c_int32, _DP,
+                                     ctypes.c_void_p]),
+    "fdlb_vn_matrix": (ctypes.c_int, [ctypes.POINTER(fdlb_vn_case), ctypes.c_double, _DP, ctypes.c_void_p]),
     "fdlb_autotune": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
 }
@@ -304,3 +314,30 @@ def fdlb_tile_shapes():
     buf = (ctypes.c_int32 * 64)()
     n = _lib.fdlb_tile_shapes(buf, 32)
     return [(buf[2 * i], buf[2 * i + 1]) for i in range(n)]
+
+
+def vn_case(state, dx, dt, tau, theta=0.0, lines=15, v=(1.0, 1.92, 2.99, 4.49)):
+    """fdlb_vn_case of a uniform state (rho, ux, uy, T) and the scheme's parameters."""
+    c = fdlb_vn_case()
+    c.rho, c.ux, c.uy, c.T = map(float, state)
+    c.dx, c.dt, c.tau, c.theta = float(dx), float(dt), float(tau), float(theta)
+    for k in range(4):
+        c.v[k] = float(v[k])
+    c.lines = int(lines)
+    return c
+
+
+def fdlb_vn_sweep(cases, phis, stream=None):
+    """Spectral radii of G(phi) (Eq. gi_j_eq) as an array (ncases, nphi)."""
+    arr = (fdlb_vn_case * len(cases))(*cases)
+    ph = np.ascontiguousarray(np.asarray(phis, dtype=np.float64))
+    out = np.zeros((len(cases), len(ph)))
+    _check(_lib.fdlb_vn_sweep(arr, len(cases), _ptr(ph), len(ph), _ptr(out), ctypes.c_void_p(stream)))
+    return out
+
+
+def fdlb_vn_matrix(case, phi, stream=None):
+    """G(phi) as (33, 33, 4) float64: real hi, real lo, imaginary hi, imaginary lo."""
+    out = np.zeros((33, 33, 4))
+    _check(_lib.fdlb_vn_matrix(ctypes.byref(case), float(phi), _ptr(out), ctypes.c_void_p(stream)))
+    return out

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdlb.so")
-SOURCES = [os.path.join(CSRC, "fdlb_kernels.hip"), os.path.join(CSRC, "fdlb_api.cpp")]
+SOURCES = [os.path.join(CSRC, "fdlb_kernels.hip"), os.path.join(CSRC, "fdlb_api.cpp"),
+           os.path.join(CSRC, "fdlb_vn.hip")]
 HEADERS = [os.path.join(CSRC, "fdlb_internal.h"), os.path.join(ROOT, "include", "fdlb.h")]
 
 # -ffp-contract=off: the float64 path reproduces a plain evaluation with no fused
