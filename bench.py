@@ -23,8 +23,11 @@ Reported in the one JSON line:
     against default tiling), and the 8192 x 2048 reflection's accuracy at 10000 steps;
     plus float32 against float64 on the same grid with Mach-5 and Mach-10 inflows, where the
     float32 storages can hold the flow;
+  - `two_step`: the same workload with two steps per pass (tblock = 2); `vn_sweep`: the
+    stability analysis of Sec. 4 on the GPU (double-double spectral radii);
   - `cpu_baseline`: the float64 oracle on a bounded slice of the headline grid, on one
-    thread and on the host threads the job may use.
+    thread and on the host threads the job may use, and one matrix of the mpmath stability
+    tool.
 """
 import argparse
 import hashlib
@@ -47,6 +50,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_0801_4169_amd", "csrc", "fdlb_kernels.hip
 # counter summaries of the interior kernel per storage (rocprofv3 FETCH_SIZE / WRITE_SIZE)
 COUNTERS = {pr: os.path.join(ROOT, "profiles", f"step_interior_{pr}_reflection_8192x2048_counters.md")
             for pr in ("f64", "f32", "f32dev")}
+COUNTERS["step2"] = os.path.join(ROOT, "profiles", "step2_f64_reflection_8192x2048_counters.md")
 COLELLA_EXACT = os.path.join(ROOT, "tests", "golden", "colella_exact_j4m.json")
 STORAGES = ("f64", "f32", "f32dev")
 
@@ -65,6 +69,7 @@ def parse():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--configs", default="1,2,3,4,5",
                     help="configuration blocks to run (comma list of 1..5; empty: none)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the two-step and stability-sweep legs")
     ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps of the CPU baseline slice (0: skip)")
     ap.add_argument("--cpu-rows", type=int, default=128, help="rows of the CPU baseline slice")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -391,6 +396,60 @@ def accuracy_blocks(P, fi, nx, ny, steps=2000):
     return out
 
 
+def two_step(P, prob, fields, single):
+    """The headline workload with two steps per pass (tblock = 2): float64 interior tiles
+    take two steps per launch with the intermediate step in LDS (bit-identical to single
+    steps).  Rate over 64 steps through the captured graphs, and the two-step kernel alone."""
+    say("two steps per pass: float64, 64 steps")
+    s = P.Solver(prob, precision="f64", tblock=2)
+    s.set_state(*fields)
+    s.step(8)
+    ms = timed_steps(s, 64)
+    k_ms = P.B.fdlb_time_kernel(s.ctx, 3, 20)
+    k_cells = P.B.fdlb_tile_cells(s.ctx, 3)
+    release(s)
+    traffic = committed_traffic("step2")
+    cells = prob["nx"] * prob["ny"]
+    rate = cells * 64 / (ms / 1e3)
+    return {"tblock": 2, "Mcell_updates_per_s": rate / 1e6, "ms_per_step": ms / 64,
+            "vs_single_step": rate / single,
+            "two_step_kernel": {"ms_per_launch": k_ms, "cells": k_cells, "steps_per_launch": 2,
+                                "hbm_frac_of_528B_per_cell_update":
+                                    ALG_BYTES["f64"] * k_cells * 2 / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                "traffic_bytes_per_cell_update": (None if traffic is None
+                                                                  else traffic / k_cells / 2),
+                                "traffic_gbs": None if traffic is None else traffic / (k_ms / 1e3) / 1e9}}
+
+
+def vn_sweep(P):
+    """The stability sweep of Sec. 4 on the GPU: spectral radius of the 33 x 33 amplification
+    matrix in double-double for 64 states (the Fig. 2 state at lambda in [0.05, 3], T and u
+    sweeps of Figs. 5, 6) x 64 phases in (0, pi]."""
+    import numpy as np
+    import torch
+    V = (1.0, 1.92, 2.99, 4.49)
+    cases = []
+    for lam in np.linspace(0.05, 3.0, 32):
+        cases.append(P.B.vn_case((2.0, 30.0, 0.0, 1.0), 3e-3, 1e-5, 1e-5, float(lam), 15, V))
+    for T in np.linspace(1.0, 25.0, 16):
+        cases.append(P.B.vn_case((2.0, 5.0, 0.0, float(T)), 3e-3, 1e-5, 1e-5, 0.0, 15, V))
+    for u in np.linspace(0.0, 30.0, 16):
+        cases.append(P.B.vn_case((2.0, float(u), 0.0, 1.0), 3e-3, 1e-5, 1e-5, 0.0, 15, V))
+    phis = np.linspace(np.pi / 64, np.pi, 64)
+    say(f"stability sweep: {len(cases)} x {len(phis)} matrices")
+    P.B.fdlb_vn_sweep(cases[:2], phis[:2])  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = P.B.fdlb_vn_sweep(cases, phis)
+    sec = time.perf_counter() - t
+    g = r.max(axis=1)
+    return {"matrices": int(r.size), "seconds": sec, "matrices_per_s": r.size / sec,
+            "arithmetic": "double-double", "converged": int(np.isfinite(r).sum()),
+            "max_growth_fig2_lambda_0.05_and_3": [float(g[0]), float(g[31])],
+            "max_growth_fig5_T_1_and_25": [float(g[32]), float(g[47])],
+            "max_growth_fig6_u_0_and_30": [float(g[48]), float(g[63])]}
+
+
 def host_cpu():
     model = platform.processor() or ""
     try:
@@ -429,7 +488,20 @@ def cpu_baseline(prob, fields, steps, rows):
     t = time.perf_counter()
     oracle.run_f(sub, f0, steps, nthreads=nthr)
     dt = time.perf_counter() - t
+    # the stability analysis of Sec. 4 as the CPU tool does it (mpmath, 30 digits), one matrix
+    import mpmath as mp
+
+    from oracle import vonneumann as vn
+    V = (1.0, 1.92, 2.99, 4.49)
+    t = time.perf_counter()
+    with mp.workdps(30):
+        vel = vn.velocities(V)
+        J = vn.dfeq_df(V, (2.0, 30.0, 0.0, 1.0), vel=vel)
+        vn.spectral_radius(vn.amplification(V, (2.0, 30.0, 0.0, 1.0), 3e-3, 1e-5, 1e-5, mp.mpf(1.0), 0.5, 15,
+                                            jac=J, vel=vel))
+    vn_s = time.perf_counter() - t
     return {"value": cells * steps / dt / 1e6, "unit": "Mcell-updates/s", "cores": nthr, "kind": "oracle",
+            "vn_mpmath_s_per_matrix": vn_s,
             "sample": f"{steps} steps of {sub['nx']}x{sub['ny']} (bottom rows of the headline grid, same sides) "
                       f"on {nthr} threads, {dt:.1f} s; {one_steps} steps on 1 thread, {dt1:.1f} s",
             "single_thread_value": cells * one_steps / dt1 / 1e6, "host_nproc": nproc, "host_cpu": model}
@@ -523,6 +595,9 @@ def main():
         blocks["cfg5"] = cfg5_accuracy(P, fi, prob, fields, head, args.steps + args.warmup)
     if 5 in wanted:
         blocks.update(accuracy_blocks(P, fi, args.nx, args.ny))
+    if not args.no_extras:
+        out["two_step"] = two_step(P, prob, fields, head["f64"]["rate"])
+        out["vn_sweep"] = vn_sweep(P)
     for pr in head:
         head[pr].pop("moments", None)
     if blocks:
