@@ -254,7 +254,7 @@ typedef struct {
 
 /* Spectral radius max |omega| of G(phi_p) for every case c and phase p, computed on the GPU
  * in double-double arithmetic (about 32 significant digits: these matrices are strongly
- * non-normal at high Mach number, and float64 eigenvalues are wrong in the third digit),
+ * non-normal at high Mach number, and float64 eigenvalues can be wrong in the second digit),
  * by a Householder reduction to Hessenberg form and the shifted QR algorithm, one
  * wavefront per matrix.  `cases`: ncases host structs; `phis`: nphi host phases (radians);
  * `radius`: host output of ncases * nphi values, case-major (NaN where the iteration did

@@ -13,7 +13,7 @@ Readings (listed in the design notes):
 
 G is strongly non-normal at high Mach number (dfeq/df has entries ~1e5 at u = 30), so its
 eigenvalues are computed at 40+ significant digits; float64 eigenvalues of the same matrix
-are wrong in the third digit.
+can be wrong in the second digit.
 """
 from __future__ import annotations
 

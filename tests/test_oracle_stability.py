@@ -1,6 +1,6 @@
 """The paper's stability findings (Sec. 4, Figs. 2, 4, 5, 6) reproduced from the amplification
 matrix of Eq. (gi_j_eq), built by ``oracle.vonneumann`` in 30-digit arithmetic (float64
-eigenvalues of these strongly non-normal 33 x 33 matrices are wrong in the third digit).
+eigenvalues of these strongly non-normal 33 x 33 matrices can be wrong in the second digit).
 
 The figures themselves are not in the available text, so their values are parity-unpinned;
 what is pinned is each ordering the text states.  The switching function is frozen at
