@@ -624,9 +624,29 @@ __device__ __forceinline__ S fetch(const Inst &I, const GLOBAL_AS char *fin, siz
     }
 }
 
+#ifndef FDLB_HALO_DMA
+#define FDLB_HALO_DMA 1  // float32 interior body: halo of all planes loaded at once, into LDS
+#endif
+#define LDS_AS __attribute__((address_space(3)))
+
+// The float32 interior body with one halo cell per thread loads the halo cells of all 33
+// planes when it loads its own cells, straight into LDS (global_load_lds: no registers), so
+// a plane's halo lines are read while the neighbouring tiles read the same lines as their
+// own and are still in L2.  Loaded one stage ahead instead, a halo line is read a whole
+// workgroup lifetime after its owner read it, and mostly comes from HBM a second time.
+template <class S, int TX, int TY, int MODE>
+constexpr bool halo_dma() {
+    return FDLB_HALO_DMA != 0 && std::is_same<S, float>::value && MODE == MODE_INTERIOR &&
+           4 * (TX + TY) <= TX * TY;
+}
+template <int TX, int TY>
+constexpr int halo_dma_width() {
+    return (4 * (TX + TY) + 63) / 64 * 64;  // whole wavefronts: a load writes 64 lanes' slots
+}
+
 template <class S, int TX, int TY, int MODE>
 __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const Tile &tile, int io,
-                                          StepSmem<S, TX, TY> &sm) {
+                                          StepSmem<S, TX, TY> &sm, S *hdma) {
     const int bin = io_in(io), bout = io_out(io);
     const Inst &I = insts[tile.inst];
     constexpr int NT = TX * TY;
@@ -681,16 +701,29 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
         }
     }
 
-    // A1: own distributions; the first halo stage is in flight during the moments
+    // A1: own distributions.  With halo_dma the halo cells of plane q go to LDS beside the
+    // own load of plane q (thread tid's halo cell lands in hdma[q * HW + tid]); otherwise the
+    // first halo stage is in flight during the moments and each stage prefetches the next.
+    constexpr bool HALL = halo_dma<S, TX, TY, MODE>();
+    constexpr int HW = halo_dma_width<TX, TY>();
+    static_assert(!HALL || (NSLOT == 1 && H0 == 0), "one halo cell per thread, indexed by tid");
     S f[NQ];
+    const int wbase = __builtin_amdgcn_readfirstlane(tid >> 6) << 6;
     static_for<0, NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         f[q] = fetch<q, MODE, S>(I, fin, pb, own);
+        if constexpr (HALL)
+            if (hl[0] >= 0)
+                __builtin_amdgcn_global_load_lds(
+                    (const GLOBAL_AS void *)(fin + (size_t)q * pb + (uint32_t)hs[0].off),
+                    (LDS_AS void *)(hdma + q * HW + wbase), 4, 0, 0);  // float only
     });
     S h0[NSLOT], h1[NSLOT];
+    if constexpr (!HALL) {
 #pragma unroll
-    for (int j = 0; j < NSLOT; ++j)
-        if (hl[j] >= 0) h0[j] = fetch<0, MODE, S>(I, fin, pb, hs[j]);
+        for (int j = 0; j < NSLOT; ++j)
+            if (hl[j] >= 0) h0[j] = fetch<0, MODE, S>(I, fin, pb, hs[j]);
+    }
 
     // A2: moments
     double n, jx, jy, E, ux, uy, T, P0;
@@ -756,16 +789,25 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
         const size_t pbs = opaque(pb);
         S *pl = &sm.buf[b][0][0][0];
         put(pl, f[0]);
+        if constexpr (HALL) {
+            // the compiler does not order LDS reads after loads into LDS: wait for this
+            // wave's loads (each wave reads back only the slots its own lanes loaded)
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (hl[0] >= 0) pl[hl[0]] = hdma[tid];
+        } else {
 #pragma unroll
-        for (int j = 0; j < NSLOT; ++j)
-            if (hl[j] >= 0) pl[hl[j]] = h0[j];
+            for (int j = 0; j < NSLOT; ++j)
+                if (hl[j] >= 0) pl[hl[j]] = h0[j];
+        }
         __syncthreads();
+        if constexpr (!HALL) {
 #pragma unroll
-        for (int j = 0; j < NSLOT; ++j)
-            if (hl[j] >= 0) {
-                h0[j] = fetch<1, MODE, S>(Is, fi, pbs, hs[j]);
-                h1[j] = fetch<5, MODE, S>(Is, fi, pbs, hs[j]);
-            }
+            for (int j = 0; j < NSLOT; ++j)
+                if (hl[j] >= 0) {
+                    h0[j] = fetch<1, MODE, S>(Is, fi, pbs, hs[j]);
+                    h1[j] = fetch<5, MODE, S>(Is, fi, pbs, hs[j]);
+                }
+        }
         compute(std::integral_constant<int, 0>{}, Is, fo, pbs, pl, static_cast<S>(cell.nF[0] * cell.c0));
         b ^= 1;
     }
@@ -782,14 +824,21 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
         S *pbuf = &sm.buf[b][1][0][0];
         put(pa, f[qa]);
         put(pbuf, f[qb]);
-#pragma unroll
-        for (int j = 0; j < NSLOT; ++j)
-            if (hl[j] >= 0) {
-                pa[hl[j]] = h0[j];
-                pbuf[hl[j]] = h1[j];
+        if constexpr (HALL) {
+            if (hl[0] >= 0) {
+                pa[hl[0]] = hdma[qa * HW + tid];
+                pbuf[hl[0]] = hdma[qb * HW + tid];
             }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NSLOT; ++j)
+                if (hl[j] >= 0) {
+                    pa[hl[j]] = h0[j];
+                    pbuf[hl[j]] = h1[j];
+                }
+        }
         __syncthreads();
-        if constexpr (st + 1 < 16) {
+        if constexpr (!HALL && st + 1 < 16) {
             constexpr int na = 1 + 8 * ((st + 1) / 4) + ((st + 1) % 4);
 #pragma unroll
             for (int j = 0; j < NSLOT; ++j)
@@ -1114,9 +1163,11 @@ template <class S, int TX, int TY, int MODE>
 __global__ __launch_bounds__(TX *TY) FDLB_STEP_WAVES_ATTR void step_kernel(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
                                                       int ntiles, int io) {
     __shared__ StepSmem<S, TX, TY> sm;
+    constexpr bool HD = halo_dma<S, TX, TY, MODE>() && !use_stream<S>();
+    __shared__ S hdma[HD ? NQ * halo_dma_width<TX, TY>() : 1];
     const Tile tile = tiles[xcd_remap(blockIdx.x, ntiles)];
     if constexpr (!use_stream<S>() || (MODE == MODE_EDGE && !stream_edge<S>()))
-        step_body<S, TX, TY, MODE>(insts, tile, io, sm);
+        step_body<S, TX, TY, MODE>(insts, tile, io, sm, hdma);
     else
         step_body_stream<S, TX, TY, MODE, FDLB_PREFETCH>(insts, tile, io, sm);
 }
