@@ -4,8 +4,9 @@ the oracle at full size: float64 every value after 8 steps, both float32 storage
 moments after 30 steps.  (The 10 000-step run itself is beyond the oracle; bench.py
 compares the storages with each other there, beside float64's own sensitivity floor.)
 
-Float32 bounds are about ten times the errors measured on MI355X (deviation storage: rel L1
-1e-8 .. 5e-8, rel Linf 3e-4; naive float32: rel L1 5e-4 .. 5e-3, rel Linf 3e-2).
+The float32 bounds are derived, not measured: `f32_bounds` bounds the error that rounding
+the stored values to float32 at every step can cause, from the oracle's own states (its
+model is pinned on the CPU against both storages emulated on the oracle).
 """
 import os
 import sys
@@ -15,6 +16,7 @@ import pytest
 
 import fdlb_inputs as fi
 import oracle
+from f32_bounds import bounds, rel_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -41,20 +43,6 @@ def workload():
     return prob, flds
 
 
-def rel_errors(m, ref):
-    """(rel L1, rel Linf) of rho and T; of ux, uy the mean and max absolute error over the
-    largest velocity component of the reference."""
-    uscale = max(float(np.max(np.abs(ref[1]))), float(np.max(np.abs(ref[2]))))
-    out = []
-    for i, (a, b) in enumerate(zip(m, ref)):
-        d = np.abs(a - b)
-        if i in (1, 2):
-            out.append((float(np.mean(d)) / uscale, float(np.max(d)) / uscale))
-        else:
-            out.append((float(np.sum(d) / np.sum(np.abs(b))), float(np.max(d) / np.max(np.abs(b)))))
-    return out
-
-
 def test_benchmark_grid_f64_every_value(P, workload):
     prob, flds = workload
     say("benchmark workload f64, 8 steps, all 33 planes")
@@ -72,25 +60,30 @@ def test_benchmark_grid_f64_every_value(P, workload):
 
 def test_benchmark_grid_float32_storages(P, workload):
     prob, flds = workload
-    say("benchmark workload f32dev and f32, 30 steps, moments")
-    ref, rbad = oracle.run_state(prob, flds, 30, nthreads=NTHR)
+    steps = 30
+    say(f"benchmark workload f32dev and f32, {steps} steps, moments against the rounding bounds")
+    f0 = oracle.init_state(prob, flds)
+    fN, rbad = oracle.run_f(prob, f0, steps, nthreads=NTHR)
     assert rbad == -1
+    ref = oracle.fields(prob, fN)
+    B = bounds(prob, f0, fN, steps + 1)  # rounded when set and after each step
+    del f0, fN
     errs = {}
     for prec in ("f32dev", "f32"):
         s = P.Solver(prob, precision=prec)
         s.set_state(*flds)
-        s.step(30)
+        s.step(steps)
         m = s.moments(allow_nonphys=True)
         _, bad = s.diag()
         s.close()
         assert not bad, prec
         errs[prec] = rel_errors(m, ref)
-    bounds = {"f32dev": ((1e-7, 3e-3), (1e-7, 3e-3), (1e-7, 3e-3), (5e-7, 3e-3)),
-              "f32": ((5e-3, 0.1), (5e-3, 0.1), (2e-3, 3e-2), (5e-2, 0.3))}
+        say(prec, {k: (f"{v[0]:.2e}", f"{v[1]:.2e}") for k, v in errs[prec].items()})
     for prec, e in errs.items():
-        for name, (l1, linf), (b1, binf) in zip(("rho", "ux", "uy", "T"), e, bounds[prec]):
-            assert l1 <= b1 and linf <= binf, f"{prec} {name}: rel L1 {l1:.3e} (bound {b1:.0e}), " \
-                                              f"rel Linf {linf:.3e} (bound {binf:.0e})"
+        for name in ("rho", "ux", "uy", "T"):
+            (l1, linf), (b1, binf) = e[name], B[prec][name]
+            assert l1 <= b1 and linf <= binf, f"{prec} {name}: rel L1 {l1:.3e} (bound {b1:.2e}), " \
+                                              f"rel Linf {linf:.3e} (bound {binf:.2e})"
     # the deviation storage is at least a thousand times closer in L1 on rho and T
-    for i in (0, 3):
-        assert errs["f32dev"][i][0] * 1e3 <= errs["f32"][i][0], errs
+    for name in ("rho", "T"):
+        assert errs["f32dev"][name][0] * 1e3 <= errs["f32"][name][0], errs

@@ -5,7 +5,8 @@ interior tiles); float32 and deviation storage: 16384 x 16384 (2^28 cells, the c
 The state is a seeded 32 x 32 pattern repeated over a periodic grid, so after any number
 of steps every cell must equal the matching cell of a 32 x 32 periodic run: the oracle's
 for float64, the library's own small run for the float32 storages (the same operations per
-cell).  Every one of the 2.7e8 cells is compared, which checks the addressing across the
+cell), which in turn must lie within the derived float32 rounding bounds of the oracle's
+small run.  Every one of the 2.7e8 cells is compared, which checks the addressing across the
 whole plane.
 """
 import gc
@@ -17,6 +18,7 @@ import pytest
 
 import fdlb_inputs as fi
 import oracle
+from f32_bounds import bounds, rel_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -81,6 +83,15 @@ def test_largest_plane_repeats_the_small_run(P, precision, nx, ny):
         s.step(steps)
         ref = s.moments()
         s.close()
+        # the small run itself against the oracle, within the float32 rounding bounds
+        p = case(PERIOD, PERIOD)
+        f0 = oracle.init_state(p, small)
+        fN, bad = oracle.run_f(p, f0, steps, nthreads=NTHR)
+        assert bad == -1
+        B = bounds(p, f0, fN, steps + 1, storages=(precision,))[precision]
+        err = rel_errors(ref, oracle.fields(p, fN))
+        for name in ("rho", "ux", "uy", "T"):
+            assert err[name][0] <= B[name][0] and err[name][1] <= B[name][1], (precision, name, err[name], B[name])
     say(precision, f"{nx}x{ny}", steps, "steps")
     big = run_big(P, precision, nx, ny, small, steps)
     say(precision, "compare every cell")
