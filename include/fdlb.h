@@ -117,6 +117,13 @@ typedef struct {
                             values are those of single steps bit for bit; the tile shape is
                             16 x 8 (shape id 8); the context borrows three buffers instead of
                             two. */
+    int32_t theta_fixed; /* 0: theta of line IV from the switching function, Eq. (add4);
+                            1: theta := theta_value in every cell and step.  Sec. 4 freezes
+                            theta to linearise the scheme for its von Neumann analysis; with it
+                            frozen, one step is linear in f around a uniform equilibrium and
+                            its Fourier symbol is the matrix of Eq. (gi_j_eq).  A test knob. */
+    int32_t pad_;
+    double theta_value;  /* finite, >= 0; read when theta_fixed = 1 */
 } fdlb_params;
 
 /* Bytes of device memory a context for these parameters borrows (both ping-pong halves,

@@ -30,12 +30,13 @@ class Solver:
     """One problem on one GPU.  ``prob`` is a problem dict (nx, ny, dx, dy, dt, tau, lam, v,
     bc, bc_state); ``precision`` is "f64", "f32" or "f32dev" (deviation storage);
     ``tile`` a shape id (0 = default); ``tblock`` steps per pass over memory (2: float64
-    interior tiles take two steps per launch, the same values as single steps)."""
+    interior tiles take two steps per launch, the same values as single steps); ``theta``
+    None, or the value theta of line IV is frozen at (Sec. 4 linearises the scheme so)."""
 
-    def __init__(self, prob, precision="f64", tile=0, device="cuda:0", tblock=1):
+    def __init__(self, prob, precision="f64", tile=0, device="cuda:0", tblock=1, theta=None):
         torch = _torch()
         self.prob = dict(prob)
-        self.params = make_params(prob, precision, tile, tblock)
+        self.params = make_params(prob, precision, tile, tblock, theta)
         self.nx, self.ny = self.params.nx, self.params.ny
         self.ncell = self.nx * self.ny
         self.dtype = np.float64 if self.params.precision == FDLB_F64 else np.float32

@@ -46,7 +46,8 @@ class fdlb_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("dt", ctypes.c_double), ("tau", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("v", ctypes.c_double * 4), ("bc", fdlb_bc * 4), ("precision", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("lines", ctypes.c_int32), ("tblock", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("lines", ctypes.c_int32), ("tblock", ctypes.c_int32),
+                ("theta_fixed", ctypes.c_int32), ("pad_", ctypes.c_int32), ("theta_value", ctypes.c_double)]
 
 
 class fdlb_vn_case(ctypes.Structure):
@@ -131,12 +132,13 @@ def _ptr(a):
     return a.ctypes.data_as(_DP)
 
 
-def make_params(prob, precision="f64", tile=0, tblock=1):
+def make_params(prob, precision="f64", tile=0, tblock=1, theta=None):
     """fdlb_params from a problem dict: nx, ny, dx, dy, dt, tau, lam, v, bc (4 kinds),
     bc_state (4 x (rho, ux, uy, T)), lower (4 x None or (kind, state, split, split_rate)),
     lines (bits of the terms of Eq. (dis_eq1) kept; default the full scheme).  ``tblock``:
     steps per pass over memory (1, or 2 for float64: interior tiles take two steps per
-    launch)."""
+    launch).  ``theta``: None for the switching function of Eq. (add4), or the value theta
+    of line IV is frozen at (Sec. 4)."""
     p = fdlb_params()
     p.nx, p.ny = int(prob["nx"]), int(prob["ny"])
     p.dx, p.dy = float(prob["dx"]), float(prob.get("dy", prob["dx"]))
@@ -156,6 +158,8 @@ def make_params(prob, precision="f64", tile=0, tblock=1):
     p.tile = int(tile)
     p.lines = int(prob.get("lines", 15))
     p.tblock = int(tblock)
+    p.theta_fixed = 0 if theta is None else 1
+    p.theta_value = 0.0 if theta is None else float(theta)
     return p
 
 

@@ -95,6 +95,8 @@ int validate(const fdlb_params &p) {
     if (p.lines < 0 || p.lines > 15) return 1;
     if (p.tblock < 0 || p.tblock > 2) return 1;
     if (p.tblock == 2 && p.precision != FDLB_F64) return 1;  // two-step passes: float64 only
+    if (p.theta_fixed != 0 && p.theta_fixed != 1) return 1;
+    if (p.theta_fixed && (!std::isfinite(p.theta_value) || p.theta_value < 0.0)) return 1;
     double vmax = 0.0;
     for (int k = 0; k < 4; ++k) {
         if (!finite_pos(p.v[k])) return 1;
@@ -208,6 +210,7 @@ void fill_constants(const fdlb_params &p, Inst &I) {
     I.cdx = p.dt / p.dx;
     I.cdy = p.dt / p.dy;
     I.lam = (lines & 8) ? p.lambda : 0.0;
+    I.thfix = p.theta_fixed ? ((lines & 8) ? p.theta_value : 0.0) : -1.0;
     for (int s = 0; s < 4; ++s) {
         const fdlb_bc &b = p.bc[s];
         I.bc[s] = b.kind;

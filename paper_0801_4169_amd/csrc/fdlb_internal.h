@@ -47,6 +47,7 @@ struct Inst {
     double k1[2][2][4], k2[2][2][4], k3[2][2][4]; // [alpha][axis=0, diag=1][speed], c >= 0
     double kk[2][2][4];                           // k1 + 2 k3 (the deviation update's weight)
     double dt, dx, dy, dtau, lam;
+    double thfix;            // theta of line IV frozen at this value (Sec. 4); < 0: Eq. (add4)
     double Fdinv[4];         // 1 / Fden (deviation path, which needs no fixed order)
     double cdx, cdy;         // dt / dx, dt / dy
     float kf[3][2][2][4];    // float copies of k1, k2, k3 (float32 path)

@@ -152,3 +152,17 @@ def test_two_step_passes_take_a_third_buffer_and_float64_only():
     assert B.fdlb_required_bytes(_sod_params(tblock=-1)) == 0
     assert B.fdlb_required_bytes(_sod_params(tblock=2, precision=B.FDLB_F32)) == 0
     assert B.fdlb_required_bytes(_sod_params(tblock=2, precision=B.FDLB_F32_DEV)) == 0
+
+
+def test_frozen_theta_is_validated():
+    """theta_fixed is 0 or 1; a frozen theta is finite and non-negative (Sec. 4 freezes theta
+    of line IV); an unfrozen context ignores theta_value."""
+    from paper_0801_4169_amd import _binding as B
+    assert B.fdlb_required_bytes(_sod_params(theta_fixed=1, theta_value=0.7)) > 0
+    assert B.fdlb_required_bytes(_sod_params(theta_fixed=1, theta_value=0.0)) > 0
+    assert B.fdlb_required_bytes(_sod_params(theta_fixed=0, theta_value=float("nan"))) > 0
+    assert B.fdlb_required_bytes(_sod_params(theta_fixed=2, theta_value=0.7)) == 0
+    assert B.fdlb_required_bytes(_sod_params(theta_fixed=1, theta_value=-0.1)) == 0
+    assert B.fdlb_required_bytes(_sod_params(theta_fixed=1, theta_value=float("inf"))) == 0
+    p = B.make_params(__import__("fdlb_inputs").sod_tube()[0], theta=0.25)
+    assert p.theta_fixed == 1 and p.theta_value == 0.25
