@@ -209,8 +209,8 @@ void fill_constants(const fdlb_params &p, Inst &I) {
     I.dtau = p.dt / p.tau;
     I.cdx = p.dt / p.dx;
     I.cdy = p.dt / p.dy;
-    I.lam = (lines & 8) ? p.lambda : 0.0;
-    I.thfix = p.theta_fixed ? ((lines & 8) ? p.theta_value : 0.0) : -1.0;
+    I.lam = (lines & 8) && !p.theta_fixed ? p.lambda : 0.0;
+    I.th0 = (lines & 8) && p.theta_fixed ? p.theta_value : 0.0;
     for (int s = 0; s < 4; ++s) {
         const fdlb_bc &b = p.bc[s];
         I.bc[s] = b.kind;

@@ -40,14 +40,14 @@ struct Inst {
     double *PW[3];
     int64_t mplane;          // elements per moment plane (ny * ppitch)
     int32_t *flag;           // sticky non-physical flag (shared by a batch)
-    int32_t *pad_ptr;
+    double th0;              // theta of line IV = lam |dP / sum P| + th0: 0 with Eq. (add4);
+                             // the frozen value (lam = 0) when theta is frozen (Sec. 4)
     double v[4], vs[4];      // speeds and speed * sqrt(2)/2 (diagonal components)
     double eax[4], edg[4];   // |v|^2 / 2 for axis and diagonal velocities
     double FA[4], FB[4], FC[4], Fden[4]; // weight polynomial constants, Eq. (fk_eq1)
     double k1[2][2][4], k2[2][2][4], k3[2][2][4]; // [alpha][axis=0, diag=1][speed], c >= 0
     double kk[2][2][4];                           // k1 + 2 k3 (the deviation update's weight)
     double dt, dx, dy, dtau, lam;
-    double thfix;            // theta of line IV frozen at this value (Sec. 4); < 0: Eq. (add4)
     double Fdinv[4];         // 1 / Fden (deviation path, which needs no fixed order)
     double cdx, cdy;         // dt / dx, dt / dy
     float kf[3][2][2][4];    // float copies of k1, k2, k3 (float32 path)

@@ -118,12 +118,13 @@ __device__ __forceinline__ bool nonphysical(const Inst &I, double n, double ux, 
     return false;
 }
 
-// Line-IV coefficient theta |kappa| (1 - |kappa|) / 2, Eqs. (add3), (add4); theta frozen at
-// thfix when thfix >= 0 (Sec. 4).
-__device__ __forceinline__ double av_coeff(double lam, double thfix, double Pm, double P0, double Pp, double u,
+// Line-IV coefficient theta |kappa| (1 - |kappa|) / 2, Eqs. (add3), (add4).  theta =
+// lam |dP / sum P| + th0: th0 = 0 with the switching function (the fused multiply-add rounds
+// the product once, so the value is that of the plain product), lam = 0 and th0 = the frozen
+// value when theta is frozen (Sec. 4).
+__device__ __forceinline__ double av_coeff(double lam, double th0, double Pm, double P0, double Pp, double u,
                                            double dt, double dr) {
-    const double sw = lam * fabs((Pp - 2.0 * P0 + Pm) / (Pp + 2.0 * P0 + Pm));
-    const double th = thfix >= 0.0 ? thfix : sw;
+    const double th = __builtin_fma(lam, fabs((Pp - 2.0 * P0 + Pm) / (Pp + 2.0 * P0 + Pm)), th0);
     const double kap = fabs(u * dt / dr);
     return th * kap * (1.0 - kap) / 2.0;
 }
@@ -753,8 +754,8 @@ __device__ __forceinline__ void step_body(const Inst *__restrict__ insts, const 
         Pym = load_P(I, Pin, PWin, x, y - 1, tnow);
         Pyp = load_P(I, Pin, PWin, x, y + 1, tnow);
     }
-    const double ax = av_coeff(I.lam, I.thfix, Pxm, P0, Pxp, ux, I.dt, I.dx);
-    const double ay = av_coeff(I.lam, I.thfix, Pym, P0, Pyp, uy, I.dt, I.dy);
+    const double ax = av_coeff(I.lam, I.th0, Pxm, P0, Pxp, ux, I.dt, I.dx);
+    const double ay = av_coeff(I.lam, I.th0, Pym, P0, Pyp, uy, I.dt, I.dy);
 
     // A4: equilibrium coefficients
     Coef C;
@@ -1021,8 +1022,8 @@ __device__ __forceinline__ void step_body_stream(const Inst *__restrict__ insts,
             Pyp = Mn[cp] * MT[cp];
         }
     }
-    const double ax = av_coeff(I.lam, I.thfix, Pxm, P0, Pxp, ux, I.dt, I.dx);
-    const double ay = av_coeff(I.lam, I.thfix, Pym, P0, Pyp, uy, I.dt, I.dy);
+    const double ax = av_coeff(I.lam, I.th0, Pxm, P0, Pxp, ux, I.dt, I.dx);
+    const double ay = av_coeff(I.lam, I.th0, Pym, P0, Pyp, uy, I.dt, I.dy);
 
     // A4: equilibrium coefficients
     Coef C;
@@ -1274,8 +1275,8 @@ __device__ __forceinline__ void step2_body(const Inst *__restrict__ insts, const
     const double Pyp = Mn[c + I.ppitch] * MT[c + I.ppitch];
     CellD cell;
     {
-        const double ax = av_coeff(I.lam, I.thfix, Pxm, P0, Pxp, ux, I.dt, I.dx);
-        const double ay = av_coeff(I.lam, I.thfix, Pym, P0, Pyp, uy, I.dt, I.dy);
+        const double ax = av_coeff(I.lam, I.th0, Pxm, P0, Pxp, ux, I.dt, I.dx);
+        const double ay = av_coeff(I.lam, I.th0, Pym, P0, Pyp, uy, I.dt, I.dy);
         Coef C;
         equilibrium_coefs(I, n, ux, uy, T, C);
         make_cell(C, ux, uy, ax, ay, I.dtau, cell);
@@ -1359,8 +1360,8 @@ __device__ __forceinline__ void step2_body(const Inst *__restrict__ insts, const
     if (tid < NTILE) {
         CellD cell2;
         {
-            const double ax = av_coeff(I.lam, I.thfix, sm.P1[ly + 1][lx], P1m, sm.P1[ly + 1][lx + 2], ux1, I.dt, I.dx);
-            const double ay = av_coeff(I.lam, I.thfix, sm.P1[ly][lx + 1], P1m, sm.P1[ly + 2][lx + 1], uy1, I.dt, I.dy);
+            const double ax = av_coeff(I.lam, I.th0, sm.P1[ly + 1][lx], P1m, sm.P1[ly + 1][lx + 2], ux1, I.dt, I.dx);
+            const double ay = av_coeff(I.lam, I.th0, sm.P1[ly][lx + 1], P1m, sm.P1[ly + 2][lx + 1], uy1, I.dt, I.dy);
             Coef C;
             equilibrium_coefs(I, n1, ux1, uy1, T1, C);
             make_cell(C, ux1, uy1, ax, ay, I.dtau, cell2);
@@ -1472,12 +1473,10 @@ __device__ __forceinline__ void dev_cell(const Inst &I, double n, double ux, dou
     d.uy = uy;
 }
 
-// Line-IV coefficient (Eqs. add3, add4) with one division; theta frozen at thfix when thfix
-// >= 0 (Sec. 4).
-__device__ __forceinline__ double av_dev(double lam, double thfix, double Pm, double P0, double Pp, double u,
+// Line-IV coefficient (Eqs. add3, add4) with one division; theta as in av_coeff.
+__device__ __forceinline__ double av_dev(double lam, double th0, double Pm, double P0, double Pp, double u,
                                          double cdr) {
-    const double sw = lam * fabs((Pp - 2.0 * P0 + Pm) / (Pp + 2.0 * P0 + Pm));
-    const double th = thfix >= 0.0 ? thfix : sw;
+    const double th = __builtin_fma(lam, fabs((Pp - 2.0 * P0 + Pm) / (Pp + 2.0 * P0 + Pm)), th0);
     const double kap = fabs(u * cdr);
     return th * kap * (1.0 - kap) * 0.5;
 }
@@ -1802,8 +1801,8 @@ __device__ __forceinline__ void step_body_dev(const Inst *__restrict__ insts, co
         if constexpr (st == 0) {
             // switching function from the neighbours' P (written before the first barrier)
             const double P0 = sm.P[own_p];
-            ax = av_dev(Is.lam, Is.thfix, sm.P[own_p - 1], P0, sm.P[own_p + 1], dc.ux, Is.cdx);
-            ay = av_dev(Is.lam, Is.thfix, sm.P[own_p - PWD], P0, sm.P[own_p + PWD], dc.uy, Is.cdy);
+            ax = av_dev(Is.lam, Is.th0, sm.P[own_p - 1], P0, sm.P[own_p + 1], dc.ux, Is.cdx);
+            ay = av_dev(Is.lam, Is.th0, sm.P[own_p - PWD], P0, sm.P[own_p + PWD], dc.uy, Is.cdy);
         }
         if constexpr (st + PD < NSTG) load_stage(std::integral_constant<int, st + PD>{}, Is, pbs);
         static_for<0, UPS>([&](auto ic) {
