@@ -37,6 +37,7 @@ import platform
 import re
 import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -309,7 +310,8 @@ def cfg4(P, fi):
     cells = sum(p["nx"] * p["ny"] for p, _ in probs)
     mom = {}
     rng_out = {"pressure_ratio": "log-uniform [10, 100]", "cells": cells}
-    cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+    cache = os.environ.get("FDLB_AUTOTUNE_CACHE",
+                           os.path.join(tempfile.gettempdir(), "fdlb_autotune_cache.json"))
     for pr in STORAGES:
         b = P.BatchSolver([p for p, _ in probs], precision=pr)
         for i, (p, flds) in enumerate(probs):
