@@ -61,6 +61,33 @@ def test_frozen_theta_bitwise_with_oracle(P, sides, tblock, lines):
     assert (lines & 8) == 0 or not np.array_equal(f_sw, f_ref)
 
 
+@pytest.mark.parametrize("precision", ["f32", "f32dev"])
+def test_frozen_theta_float32_storages_within_rounding_bounds(P, precision):
+    """The float32 storages with theta frozen against the oracle's frozen-theta run, within
+    the float32 rounding bounds derived from the oracle's states (and the storage really
+    follows the frozen theta: the switching function's run lies outside them)."""
+    from f32_bounds import bounds, rel_errors
+    say("frozen theta 0.6", precision)
+    nx, ny, steps = 140, 44, 5
+    prob = fi.problem(nx, ny, 2e-3, 2e-5, 3e-5, 1.5, ("periodic",) * 4)
+    flds = fi.random_fields(nx, ny, seed=5)
+    s = P.Solver(prob, precision=precision, theta=0.6)
+    s.set_state(*flds)
+    s.step(steps)
+    m = s.moments()
+    s.close()
+    f0 = oracle.init_state(prob, flds)
+    fN, bad = oracle.run_f(prob, f0, steps, nthreads=NTHR, theta_fixed=True, theta_value=0.6)
+    assert bad == -1
+    B = bounds(prob, f0, fN, steps + 1, storages=(precision,))[precision]
+    err = rel_errors(m, oracle.fields(prob, fN))
+    for name in ("rho", "ux", "uy", "T"):
+        assert err[name][0] <= B[name][0] and err[name][1] <= B[name][1], (name, err[name], B[name])
+    f_sw, _ = oracle.run_f(prob, f0, steps, nthreads=NTHR)
+    far = rel_errors(m, oracle.fields(prob, f_sw))
+    assert any(far[k][1] > B[k][1] for k in far), (far, B)
+
+
 def test_linearised_gpu_step_is_the_amplification_matrix(P):
     """Uniform equilibrium on an 8-periodic strip (4 rows, uniform in y, so the y lines vanish
     as for a wave along x), perturbed by eps Re(w_m exp(i phi_m x)) for phi_m = 2 pi m / 8,
