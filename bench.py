@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--configs", default="1,2,3,4,5",
                     help="configuration blocks to run (comma list of 1..5; empty: none)")
     ap.add_argument("--no-extras", action="store_true", help="skip the two-step and stability-sweep legs")
-    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps of the CPU baseline slice (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=160, help="oracle steps of the CPU baseline slice (0: skip)")
     ap.add_argument("--cpu-rows", type=int, default=128, help="rows of the CPU baseline slice")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (calibrates the HBM "
