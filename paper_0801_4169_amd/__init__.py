@@ -164,11 +164,12 @@ def _autotune(solver, trial_steps, shape_ids, groups, cache, key):
 
 
 class BatchSolver:
-    """k independent problems advanced by one launch per step."""
+    """k independent problems advanced by one launch per step (per tile kind).  ``tblock``
+    as for Solver, for every instance (float64)."""
 
-    def __init__(self, probs, precision="f32", tile=0, device="cuda:0"):
+    def __init__(self, probs, precision="f32", tile=0, device="cuda:0", tblock=1):
         torch = _torch()
-        self.params = [make_params(p, precision, tile) for p in probs]
+        self.params = [make_params(p, precision, tile, tblock) for p in probs]
         self.sizes = [(p.ny, p.nx) for p in self.params]
         self.dtype = np.float64 if self.params[0].precision == FDLB_F64 else np.float32
         nbytes = B.fdlb_batch_required_bytes(self.params)
