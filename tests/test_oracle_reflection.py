@@ -86,3 +86,25 @@ def test_sharp_start_fails_and_smoothed_start_runs(width):
         assert bad == -1
         T = oracle.fields(p, f)[3]
         assert T.min() > 0.4
+
+
+@pytest.mark.parametrize("dt", [1e-5, 2e-6])
+def test_mach20_double_mach_reflection_fails_at_the_wall_foot(dt):
+    """The Mach-20 double Mach reflection of Sec. 5.2.2 (smoothed start, lambda = 20,
+    dt = tau) turns non-physical first on the wall at the foot of the incident shock, a few
+    cells after the wall begins at x = 0.08 (80 cells), at t of about 1.9e-4 for both time
+    steps: a feature of the flow at the scheme's reading, not of the step size."""
+    prob, flds, _ = fi.double_mach(mach=20.0, lam=20.0, width=2.0, dt=dt, tau=dt)
+    f = oracle.init_state(prob, flds)
+    first = None
+    for step in range(1, int(round(3e-4 / dt)) + 1):
+        f, _ = oracle.run_f(prob, f, 1, nthreads=NTHR, step0=step - 1)
+        T = oracle.fields(prob, f)[3]
+        bad = np.argwhere(~(T > 0))
+        if len(bad):
+            first = (step, bad)
+            break
+    assert first is not None
+    step, bad = first
+    assert 1.5e-4 < step * dt < 2.5e-4, step * dt
+    assert all(y <= 1 and 82 <= x <= 95 for y, x in bad.tolist()), bad.tolist()
