@@ -165,11 +165,13 @@ def _autotune(solver, trial_steps, shape_ids, groups, cache, key):
 
 class BatchSolver:
     """k independent problems advanced by one launch per step (per tile kind).  ``tblock``
-    as for Solver, for every instance (float64)."""
+    as for Solver, for every instance (float64); ``thetas`` None, or per instance None or
+    the value theta of line IV is frozen at (Sec. 4)."""
 
-    def __init__(self, probs, precision="f32", tile=0, device="cuda:0", tblock=1):
+    def __init__(self, probs, precision="f32", tile=0, device="cuda:0", tblock=1, thetas=None):
         torch = _torch()
-        self.params = [make_params(p, precision, tile, tblock) for p in probs]
+        thetas = thetas if thetas is not None else [None] * len(probs)
+        self.params = [make_params(p, precision, tile, tblock, th) for p, th in zip(probs, thetas)]
         self.sizes = [(p.ny, p.nx) for p in self.params]
         self.dtype = np.float64 if self.params[0].precision == FDLB_F64 else np.float32
         nbytes = B.fdlb_batch_required_bytes(self.params)

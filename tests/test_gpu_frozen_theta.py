@@ -88,6 +88,29 @@ def test_frozen_theta_float32_storages_within_rounding_bounds(P, precision):
     assert any(far[k][1] > B[k][1] for k in far), (far, B)
 
 
+def test_frozen_theta_per_batch_instance(P):
+    """In one batch, an instance with theta frozen and one with the switching function:
+    each equals its own single run, bit for bit (theta is an instance constant)."""
+    say("batch: frozen and switching-function instances")
+    st = [(1.1, 0.4, -0.1, 0.9), (1.0, 0.2, 0.05, 1.1), (1.0, 0.3, 0.0, 1.0), (0.9, 0.35, -0.2, 1.2)]
+    cases = [(fi.problem(140, 44, 2e-3, 2e-5, 3e-5, 1.5, SIDES[0], st), fi.random_fields(140, 44, seed=31), 0.6),
+             (fi.problem(96, 40, 2e-3, 2e-5, 3e-5, 1.5, SIDES[1], st), fi.random_fields(96, 40, seed=32), None)]
+    b = P.BatchSolver([p for p, _, _ in cases], precision="f64", thetas=[th for _, _, th in cases])
+    for i, (_, flds, _) in enumerate(cases):
+        b.set_state(i, *flds)
+    b.step(9)
+    got = [b.moments(i) for i in range(len(cases))]
+    b.close()
+    for i, (prob, flds, th) in enumerate(cases):
+        s = P.Solver(prob, precision="f64", theta=th)
+        s.set_state(*flds)
+        s.step(9)
+        ref = s.moments()
+        s.close()
+        for a, r in zip(got[i], ref):
+            assert np.array_equal(a, r), i
+
+
 def test_linearised_gpu_step_is_the_amplification_matrix(P):
     """Uniform equilibrium on an 8-periodic strip (4 rows, uniform in y, so the y lines vanish
     as for a wave along x), perturbed by eps Re(w_m exp(i phi_m x)) for phi_m = 2 pi m / 8,
